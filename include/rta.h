@@ -1,0 +1,164 @@
+/*
+ * rta.h -- C ABI of librta: real-time multichannel partitioned convolution
+ * (uniform and non-uniform partitioned overlap-save with a frequency-domain
+ * delay line) on one AMD Instinct MI355X (gfx950).
+ *
+ * Operation (paper Sec. III-A Eq. 1-2): for Q input channels x_q and L output
+ * channels,
+ *
+ *     y_l[n] = sum_{q<Q} sum_{j<n_h(q,l)} h_ql[j] * x_q[n-j]      (causal,
+ *                                                     zero history before n=0)
+ *
+ * computed block by block: call k of rta_process() consumes input samples
+ * [kB, (k+1)B) of every input and returns output samples [kB, (k+1)B) of
+ * every output, with no added latency.  The filter matrix is split into
+ * partitions whose spectra are multiplied with a frequency-domain delay line
+ * of input spectra (Sec. IV steps 1-3, after Wefers); non-uniform schemes
+ * (Sec. III-B, last paragraphs) add longer partitions for later filter
+ * segments, whose delays are realized in the time domain.
+ *
+ * Conventions for every entry point:
+ *   - Return value: RTA_OK (0) or a negative rta_status.  No exception or
+ *     signal crosses the ABI; rta_strerror() names the code.
+ *   - A context is used by one host thread at a time.  Distinct contexts are
+ *     independent and may be used from different threads.
+ *   - After RTA_E_DEVICE the context is poisoned: every later call except
+ *     rta_query/rta_destroy returns RTA_E_DEVICE.
+ *   - Argument validation happens before any HIP call, so RTA_E_ARG never
+ *     touches the GPU.
+ */
+#ifndef RTA_H
+#define RTA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rta_ctx rta_ctx;
+
+typedef enum rta_status {
+    RTA_OK = 0,
+    RTA_E_ARG = -1,         /* invalid argument (NULL, size, scheme, dtype) */
+    RTA_E_NOMEM = -2,       /* device or pinned host allocation failed      */
+    RTA_E_RANGE = -3,       /* a filter spectrum exceeds the FP16 range      */
+    RTA_E_DEVICE = -4,      /* a HIP runtime call failed; context poisoned   */
+    RTA_E_STATE = -5,       /* call not valid in the context's current state */
+    RTA_E_UNSUPPORTED = -6  /* valid request this build does not implement   */
+} rta_status;
+
+/* Storage type of the filter spectra.  Input spectra, the multiply-
+ * accumulate and both FFTs always run in FP32; the conversion to FP16/BF16
+ * rounds to nearest-even and keeps subnormals. */
+typedef enum rta_dtype { RTA_FP32 = 0, RTA_FP16 = 1, RTA_BF16 = 2 } rta_dtype;
+
+/* rta_create() flags. */
+#define RTA_FLAG_SPIKE   0x1u  /* NUPC: do a tier's whole frame in the block
+                                  its input completes (needs offset >= size-B
+                                  ... see rta_scheme); default spreads it.  */
+#define RTA_FLAG_NO_GRAPH 0x2u /* rta_process(): launch eagerly instead of
+                                  replaying a captured hipGraph.            */
+
+/* Partition scheme (Sec. III-B: uniform and non-uniform partitioning).
+ *   size[t]  partition length of tier t in samples; size[0] must equal the
+ *            block length, every size is a power of two and a multiple of
+ *            the block, and sizes strictly increase.
+ *   count[t] number of partitions of tier t; count[n_tiers-1] == 0 means
+ *            "as many as the longest filter needs".
+ * Tier t covers filter taps [o_t, o_t + count[t]*size[t]) with o_0 = 0 and
+ * o_{t+1} = o_t + count[t]*size[t].  For t >= 1 the scheme must satisfy
+ * o_t >= 2*size[t] - block (the frame's work is then spread over the
+ * size[t]/block blocks before its first output sample is due).
+ * A NULL scheme means uniform partitioning with size[0] = block, i.e. the
+ * paper's UPOLS with n_k = n_x and n_f = 2 n_x (Sec. IV). */
+typedef struct rta_scheme {
+    int32_t n_tiers;
+    const int32_t* size;
+    const int32_t* count;
+} rta_scheme;
+
+#define RTA_MAX_TIERS 8
+
+typedef struct rta_info {
+    double fs;                    /* sampling rate given at creation       */
+    double deadline_us;           /* block / fs in microseconds (Sec. I)   */
+    int32_t block, n_in, n_out, n_tiers, spectra_dtype, n_phases;
+    int32_t tier_size[RTA_MAX_TIERS];
+    int32_t tier_count[RTA_MAX_TIERS];
+    int64_t tier_offset[RTA_MAX_TIERS];
+    int64_t blocks_done;          /* blocks processed since create/reset   */
+    int64_t spectra_bytes;        /* filter spectra resident in HBM        */
+    int64_t device_bytes;         /* all device memory held by the context */
+    double  h_bytes_per_block;    /* filter-spectrum bytes streamed per
+                                     block, averaged over the tier phases  */
+    double  x_bytes_per_block;    /* input-spectrum (FDL) bytes read per
+                                     block, counted once per (q, slot)     */
+    double  io_bytes_per_block;   /* input block + output block bytes      */
+    double  cmacs_per_block;      /* complex multiply-accumulates / block  */
+    int32_t grid;                 /* workgroups per block launch           */
+    int32_t outputs_per_group;    /* outputs sharing one input-spectrum
+                                     load in the multiply-accumulate       */
+    int32_t rows_per_item;        /* partitions per workgroup work item    */
+    int32_t poisoned;             /* 1 after RTA_E_DEVICE                  */
+} rta_info;
+
+/* Create a context.
+ *   out      receives the context (set to NULL on failure).
+ *   fs       sampling rate in Hz (> 0); used for deadline_us only.
+ *   block    B, samples per call; power of two in [16, 4096].
+ *   scheme   partition scheme (see rta_scheme) or NULL for UPOLS.
+ *   n_in     Q >= 1 input channels;  n_out  L >= 1 output channels.
+ *   filters  n_in*n_out host pointers, row-major [in][out]: filters[q*n_out+l]
+ *            points to lengths[q*n_out+l] FP32 taps of h_ql.  A NULL pointer
+ *            or a zero length means "no path".  The taps are copied during
+ *            the call; the caller may free them on return.
+ *   lengths  n_in*n_out tap counts (>= 0).
+ *   spectra  rta_dtype of the stored filter spectra.
+ *   flags    RTA_FLAG_* bits.
+ * Allocates all device memory (spectra, delay lines, rings) on the current
+ * HIP device and builds the filter spectra there.  Returns RTA_E_RANGE if
+ * FP16 storage is requested and a spectrum value exceeds 65504 in
+ * magnitude. */
+int rta_create(rta_ctx** out, double fs, int32_t block,
+               const rta_scheme* scheme, int32_t n_in, int32_t n_out,
+               const float* const* filters, const int64_t* lengths,
+               int32_t spectra, uint32_t flags);
+
+/* Process one block, host memory in and out, synchronously.
+ *   in   [n_in][block] FP32 host array (row-major), read during the call.
+ *   out  [n_out][block] FP32 host array, valid on return.
+ * Copies the input block to the device, runs the block on the context's own
+ * stream (a captured hipGraph unless RTA_FLAG_NO_GRAPH), copies the output
+ * back and waits.  Must not be interleaved with rta_process_device() calls
+ * that are still in flight on another stream. */
+int rta_process(rta_ctx* ctx, const float* in, float* out);
+
+/* Process one block, device memory in and out, stream-ordered.
+ *   d_in    [n_in][block] FP32 device array; d_out [n_out][block] FP32.
+ *   stream  hipStream_t to launch on (NULL: the context's own stream).
+ * Enqueues the block and returns without waiting; d_out is valid once the
+ * stream reaches this point.  Successive calls must be ordered on one
+ * stream (the block index lives in device memory and advances per call). */
+int rta_process_device(rta_ctx* ctx, const float* d_in, float* d_out,
+                       void* stream);
+
+/* Zero all delay lines, input history, output rings and the block index, as
+ * if the context had just been created.  Synchronous. */
+int rta_reset(rta_ctx* ctx);
+
+/* Fill *info with the context's geometry and counters.  Synchronizes the
+ * context's stream to read the block index. */
+int rta_query(rta_ctx* ctx, rta_info* info);
+
+/* Release the context and all its memory.  NULL is accepted (no-op). */
+int rta_destroy(rta_ctx* ctx);
+
+/* Static, NUL-terminated description of a status code. */
+const char* rta_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RTA_H */

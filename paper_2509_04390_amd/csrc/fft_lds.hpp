@@ -1,0 +1,136 @@
+// fft_lds.hpp -- workgroup-cooperative FFTs staged in LDS (gfx950, wave64).
+//
+// Complex FFT: Stockham autosort, radix 4 with one radix-2 stage when log2 N
+// is odd, ping-ponging between two LDS buffers so the result comes out in
+// natural order without a bit-reversal pass.  Stage with radix R and
+// sub-transform length Ns (Ns = 1, R, R^2, ...): element j of the stage
+// (j < N/R, k = j mod Ns) reads a[j + r N/R], multiplies by W_{R Ns}^{r k},
+// does an R-point DFT and writes b[(j - k) R + k + r Ns].
+//
+// Real FFT of 2P samples via one P-point complex FFT (the usual even/odd
+// split): z[m] = w[2m] + i w[2m+1], Z = FFT_P(z), then
+//   E = (Z[k] + conj Z[P-k]) / 2,  O = -i (Z[k] - conj Z[P-k]) / 2,
+//   X[k] = E + W_2P^k O,  X[P-k] = conj(E - W_2P^k O).
+// The P bins are stored "packed": bin 0 carries the two real values DC and
+// Nyquist as (X[0], X[P]); bins 1..P-1 are the ordinary complex bins.  The
+// inverse undoes the split and leaves the 1/(2P) factor to the caller.
+//
+// Twiddles are host-generated in FP64 and rounded once to FP32; a tier's
+// table holds W_P^j (j < P) followed by W_2P^k (k < P), W_N = exp(-2 pi i/N).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace rta {
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+
+// Complex FFT of length N = 2^logN held in LDS buffer `a`; `b` is LDS scratch
+// of the same length.  INV selects exp(+2 pi i/N) twiddles (unnormalized).
+// Every thread of the workgroup must call it; it returns the buffer that
+// holds the result and ends with a barrier.
+template <bool INV>
+__device__ float2* fft_stockham(float2* a, float2* b, int N, int logN,
+                                const float2* __restrict__ tw) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  int Ns = 1, rem = logN;
+  while (rem > 0) {
+    if (rem >= 2) {
+      const int quarter = N >> 2;
+      const int ts = N / (Ns << 2);
+      for (int j = tid; j < quarter; j += nt) {
+        const int k = j & (Ns - 1);
+        float2 v0 = a[j], v1 = a[j + quarter], v2 = a[j + 2 * quarter], v3 = a[j + 3 * quarter];
+        if (Ns > 1) {
+          float2 w1 = tw[k * ts], w2 = tw[2 * k * ts], w3 = tw[3 * k * ts];
+          if (INV) { w1.y = -w1.y; w2.y = -w2.y; w3.y = -w3.y; }
+          v1 = cmul(v1, w1); v2 = cmul(v2, w2); v3 = cmul(v3, w3);
+        }
+        const float2 s02 = cadd(v0, v2), d02 = csub(v0, v2);
+        const float2 s13 = cadd(v1, v3), d13 = csub(v1, v3);
+        // forward: -i * d13 ; inverse: +i * d13
+        const float2 jd = INV ? make_float2(-d13.y, d13.x) : make_float2(d13.y, -d13.x);
+        const int base = ((j - k) << 2) + k;
+        b[base] = cadd(s02, s13);
+        b[base + Ns] = cadd(d02, jd);
+        b[base + 2 * Ns] = csub(s02, s13);
+        b[base + 3 * Ns] = csub(d02, jd);
+      }
+      Ns <<= 2;
+      rem -= 2;
+    } else {
+      const int half = N >> 1;
+      const int ts = N / (Ns << 1);
+      for (int j = tid; j < half; j += nt) {
+        const int k = j & (Ns - 1);
+        float2 v0 = a[j], v1 = a[j + half];
+        if (Ns > 1) {
+          float2 w = tw[k * ts];
+          if (INV) w.y = -w.y;
+          v1 = cmul(v1, w);
+        }
+        const int base = ((j - k) << 1) + k;
+        b[base] = cadd(v0, v1);
+        b[base + Ns] = csub(v0, v1);
+      }
+      Ns <<= 1;
+      rem -= 1;
+    }
+    __syncthreads();
+    float2* t = a; a = b; b = t;
+  }
+  return a;
+}
+
+// Packed spectrum of the 2P real samples whose complex FFT Z (length P) is in
+// `Z`; writes P packed bins to `X` (LDS or global, must not alias Z).
+// tw2 = W_2P^k table.  Ends with a barrier.
+__device__ __forceinline__ void rfft_post(const float2* Z, float2* X, int P,
+                                          const float2* __restrict__ tw2) {
+  for (int k = threadIdx.x; k <= (P >> 1); k += blockDim.x) {
+    if (k == 0) {
+      const float2 z = Z[0];
+      X[0] = make_float2(z.x + z.y, z.x - z.y);
+      continue;
+    }
+    const float2 zk = Z[k], zm = cconj(Z[P - k]);
+    const float2 E = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y + zm.y));
+    const float2 d = csub(zk, zm);
+    const float2 O = make_float2(0.5f * d.y, -0.5f * d.x);  // -i d / 2
+    const float2 wO = cmul(tw2[k], O);
+    X[k] = cadd(E, wO);
+    if (k != P - k) X[P - k] = cconj(csub(E, wO));
+  }
+  __syncthreads();
+}
+
+// Inverse of rfft_post without the 1/2 factors: from packed bins X builds
+// Z' = 2 Z so that IFFT_P(Z') / (2P) = z, z[m] = w[2m] + i w[2m+1].
+// Ends with a barrier.
+__device__ __forceinline__ void irfft_pre(const float2* X, float2* Z, int P,
+                                          const float2* __restrict__ tw2) {
+  for (int k = threadIdx.x; k <= (P >> 1); k += blockDim.x) {
+    if (k == 0) {
+      const float2 x = X[0];  // (DC, Nyquist)
+      Z[0] = make_float2(x.x + x.y, x.x - x.y);
+      continue;
+    }
+    const float2 xk = X[k], xm = cconj(X[P - k]);
+    const float2 E = cadd(xk, xm);
+    const float2 O = cmul(csub(xk, xm), cconj(tw2[k]));
+    const float2 iO = make_float2(-O.y, O.x);
+    Z[k] = cadd(E, iO);
+    if (k != P - k) {
+      const float2 iOc = make_float2(O.y, O.x);  // i * conj(O)
+      Z[P - k] = cadd(cconj(E), iOc);
+    }
+  }
+  __syncthreads();
+}
+
+}  // namespace rta

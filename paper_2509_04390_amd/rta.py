@@ -1,0 +1,263 @@
+"""ctypes binding of librta (include/rta.h): argument marshalling only.
+
+Every entry point keeps the C name.  All computation happens in the HIP
+library; importing this module fails loudly when librta.so has not been built,
+and there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librta.so")
+if not os.path.exists(_LIB_PATH):
+    raise ImportError(f"{_LIB_PATH} is missing: build it first "
+                      "(python -c 'import __graft_entry__ as g; g.build()')")
+_lib = ctypes.CDLL(_LIB_PATH)
+
+RTA_OK = 0
+RTA_E_ARG = -1
+RTA_E_NOMEM = -2
+RTA_E_RANGE = -3
+RTA_E_DEVICE = -4
+RTA_E_STATE = -5
+RTA_E_UNSUPPORTED = -6
+
+RTA_FP32, RTA_FP16, RTA_BF16 = 0, 1, 2
+DTYPES = {"fp32": RTA_FP32, "fp16": RTA_FP16, "bf16": RTA_BF16}
+
+RTA_FLAG_SPIKE = 0x1
+RTA_FLAG_NO_GRAPH = 0x2
+RTA_MAX_TIERS = 8
+
+EXPORTED = ("rta_create", "rta_process", "rta_process_device", "rta_reset",
+            "rta_query", "rta_destroy", "rta_strerror")
+
+
+class rta_scheme(ctypes.Structure):
+    _fields_ = [("n_tiers", ctypes.c_int32),
+                ("size", ctypes.POINTER(ctypes.c_int32)),
+                ("count", ctypes.POINTER(ctypes.c_int32))]
+
+
+class rta_info(ctypes.Structure):
+    _fields_ = [("fs", ctypes.c_double),
+                ("deadline_us", ctypes.c_double),
+                ("block", ctypes.c_int32), ("n_in", ctypes.c_int32),
+                ("n_out", ctypes.c_int32), ("n_tiers", ctypes.c_int32),
+                ("spectra_dtype", ctypes.c_int32), ("n_phases", ctypes.c_int32),
+                ("tier_size", ctypes.c_int32 * RTA_MAX_TIERS),
+                ("tier_count", ctypes.c_int32 * RTA_MAX_TIERS),
+                ("tier_offset", ctypes.c_int64 * RTA_MAX_TIERS),
+                ("blocks_done", ctypes.c_int64),
+                ("spectra_bytes", ctypes.c_int64),
+                ("device_bytes", ctypes.c_int64),
+                ("h_bytes_per_block", ctypes.c_double),
+                ("x_bytes_per_block", ctypes.c_double),
+                ("io_bytes_per_block", ctypes.c_double),
+                ("cmacs_per_block", ctypes.c_double),
+                ("grid", ctypes.c_int32),
+                ("outputs_per_group", ctypes.c_int32),
+                ("rows_per_item", ctypes.c_int32),
+                ("poisoned", ctypes.c_int32)]
+
+
+_fp = ctypes.POINTER(ctypes.c_float)
+_lib.rta_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_double, ctypes.c_int32,
+                            ctypes.POINTER(rta_scheme), ctypes.c_int32, ctypes.c_int32,
+                            ctypes.POINTER(_fp), ctypes.POINTER(ctypes.c_int64),
+                            ctypes.c_int32, ctypes.c_uint32]
+_lib.rta_process.argtypes = [ctypes.c_void_p, _fp, _fp]
+_lib.rta_process_device.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p]
+_lib.rta_reset.argtypes = [ctypes.c_void_p]
+_lib.rta_query.argtypes = [ctypes.c_void_p, ctypes.POINTER(rta_info)]
+_lib.rta_destroy.argtypes = [ctypes.c_void_p]
+_lib.rta_strerror.argtypes = [ctypes.c_int]
+_lib.rta_strerror.restype = ctypes.c_char_p
+for _f in ("rta_create", "rta_process", "rta_process_device", "rta_reset", "rta_query",
+           "rta_destroy"):
+    getattr(_lib, _f).restype = ctypes.c_int
+
+
+class RtaError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {rta_strerror(status)} ({status})")
+
+
+def _check(status: int, where: str) -> None:
+    if status != RTA_OK:
+        raise RtaError(status, where)
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def deadline_us(block: int, fs: float) -> float:
+    """Buffer latency B/fs in microseconds, the per-block budget (Sec. I)."""
+    return 1e6 * block / fs
+
+
+# ----------------------------------------------------------------------------
+# C entry points under their own names
+# ----------------------------------------------------------------------------
+
+def rta_strerror(status: int) -> str:
+    return _lib.rta_strerror(int(status)).decode()
+
+
+def rta_create(fs: float, block: int, scheme: Optional[Sequence[Sequence[int]]],
+               n_in: int, n_out: int, filters, lengths=None, spectra="fp32",
+               flags: int = 0) -> ctypes.c_void_p:
+    """filters: Q x L nested list of 1-D float32 arrays (None/empty = no path),
+    or a flat length-Q*L list in [in][out] order.  scheme: None (UPOLS) or a
+    sequence of (size, count) tiers.  Returns the opaque context handle."""
+    flat = _flatten(filters, n_in, n_out)
+    keep = [np.ascontiguousarray(f, dtype=np.float32) if f is not None and len(f) else None
+            for f in flat]
+    ptrs = (_fp * len(keep))()
+    lens = (ctypes.c_int64 * len(keep))()
+    for i, f in enumerate(keep):
+        ptrs[i] = f.ctypes.data_as(_fp) if f is not None else None
+        lens[i] = 0 if f is None else f.size
+    if lengths is not None:
+        for i, n in enumerate(lengths):
+            lens[i] = int(n)
+    sch = None
+    if scheme is not None:
+        sizes = (ctypes.c_int32 * len(scheme))(*[int(s) for s, _ in scheme])
+        counts = (ctypes.c_int32 * len(scheme))(*[int(c) for _, c in scheme])
+        sch = rta_scheme(len(scheme), sizes, counts)
+    dtype = DTYPES[spectra] if isinstance(spectra, str) else int(spectra)
+    ctx = ctypes.c_void_p()
+    st = _lib.rta_create(ctypes.byref(ctx), float(fs), int(block),
+                         ctypes.byref(sch) if sch is not None else None,
+                         int(n_in), int(n_out), ptrs, lens, dtype, int(flags))
+    _check(st, "rta_create")
+    return ctx
+
+
+def rta_process(ctx, inp: np.ndarray, out: np.ndarray) -> None:
+    """inp: [n_in][block] float32 (C-contiguous); out: [n_out][block] float32."""
+    assert inp.dtype == np.float32 and inp.flags.c_contiguous
+    assert out.dtype == np.float32 and out.flags.c_contiguous
+    _check(_lib.rta_process(ctx, inp.ctypes.data_as(_fp), out.ctypes.data_as(_fp)),
+           "rta_process")
+
+
+def rta_process_device(ctx, d_in: int, d_out: int, stream: int = 0) -> None:
+    """Device pointers (ints, e.g. torch data_ptr()) and a hipStream_t handle."""
+    _check(_lib.rta_process_device(ctx, ctypes.c_void_p(d_in), ctypes.c_void_p(d_out),
+                                   ctypes.c_void_p(stream or None)), "rta_process_device")
+
+
+def rta_reset(ctx) -> None:
+    _check(_lib.rta_reset(ctx), "rta_reset")
+
+
+def rta_query(ctx) -> dict:
+    info = rta_info()
+    _check(_lib.rta_query(ctx, ctypes.byref(info)), "rta_query")
+    d = {}
+    for name, _ in rta_info._fields_:
+        v = getattr(info, name)
+        d[name] = list(v)[:info.n_tiers] if hasattr(v, "__len__") else v
+    return d
+
+
+def rta_destroy(ctx) -> None:
+    _check(_lib.rta_destroy(ctx), "rta_destroy")
+
+
+def _flatten(filters, n_in: int, n_out: int) -> List:
+    """Q x L nested lists -> flat [in][out] list; a flat list passes through."""
+    if len(filters) == n_in and all(isinstance(r, (list, tuple)) for r in filters):
+        flat = [f for row in filters for f in row]
+    else:
+        flat = list(filters)
+    if len(flat) != n_in * n_out:
+        raise ValueError(f"expected {n_in}x{n_out} filters, got {len(flat)}")
+    return flat
+
+
+# ----------------------------------------------------------------------------
+# Convenience wrapper
+# ----------------------------------------------------------------------------
+
+class Convolver:
+    """One context: ``process`` (host block), ``process_device`` (torch
+    tensors on the current stream) and ``run`` (whole host signal)."""
+
+    def __init__(self, filters, block: int, fs: float = 48000.0, scheme=None,
+                 spectra="fp32", flags: int = 0):
+        self.n_in = len(filters)
+        self.n_out = len(filters[0])
+        self.block = block
+        self.ctx = rta_create(fs, block, scheme, self.n_in, self.n_out, filters,
+                              spectra=spectra, flags=flags)
+
+    def close(self):
+        if self.ctx is not None:
+            rta_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        return rta_query(self.ctx)
+
+    def reset(self):
+        rta_reset(self.ctx)
+
+    def process(self, block_in: np.ndarray) -> np.ndarray:
+        out = np.empty((self.n_out, self.block), np.float32)
+        rta_process(self.ctx, np.ascontiguousarray(block_in, dtype=np.float32), out)
+        return out
+
+    def process_device(self, d_in, d_out, stream=None) -> None:
+        """d_in/d_out: contiguous float32 torch CUDA tensors."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        assert d_in.is_contiguous() and d_out.is_contiguous()
+        assert d_in.dtype == torch.float32 and d_out.dtype == torch.float32
+        assert d_in.numel() == self.n_in * self.block and d_out.numel() == self.n_out * self.block
+        rta_process_device(self.ctx, d_in.data_ptr(), d_out.data_ptr(), stream.cuda_stream)
+
+    def run(self, x: np.ndarray) -> np.ndarray:
+        """Stream a whole host signal [n_in][n*block] through rta_process."""
+        x = np.asarray(x, np.float32)
+        nb = x.shape[1] // self.block
+        y = np.empty((self.n_out, nb * self.block), np.float32)
+        for b in range(nb):
+            y[:, b * self.block:(b + 1) * self.block] = self.process(
+                x[:, b * self.block:(b + 1) * self.block])
+        return y
+
+    def run_device(self, x: np.ndarray):
+        """Stream a whole signal with device-resident blocks (torch tensors);
+        returns the host output."""
+        import torch
+        x = torch.from_numpy(np.ascontiguousarray(x, np.float32)).cuda()
+        nb = x.shape[1] // self.block
+        xb = x[:, :nb * self.block].reshape(self.n_in, nb, self.block).permute(1, 0, 2).contiguous()
+        yb = torch.empty((nb, self.n_out, self.block), dtype=torch.float32, device="cuda")
+        for b in range(nb):
+            self.process_device(xb[b], yb[b])
+        torch.cuda.synchronize()
+        return yb.permute(1, 0, 2).reshape(self.n_out, nb * self.block).cpu().numpy()

@@ -1,0 +1,98 @@
+"""C ABI checks that need no GPU: the library loads, exports every entry point
+the header declares, validates arguments before touching HIP, and the host
+helpers reproduce the buffer latencies printed in Table I."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rta.h")
+
+
+@pytest.fixture(scope="module")
+def rta():
+    from paper_2509_04390_amd import rta as mod
+    return mod
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rta_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_expected_entry_points(rta):
+    assert declared_functions() == sorted(rta.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol(rta):
+    lib = ctypes.CDLL(rta.library_path())
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", rta.library_path()],
+                         capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (rta_[a-z_]+)\b", out))
+    assert set(declared_functions()) <= exported
+
+
+def test_strerror_names_every_status(rta):
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert rta.rta_strerror(code) and rta.rta_strerror(code) != "unknown status"
+    assert rta.rta_strerror(-99) == "unknown status"
+
+
+def test_destroy_null_and_null_handles_are_rejected(rta):
+    lib = rta._lib
+    assert lib.rta_destroy(None) == 0
+    assert lib.rta_process(None, None, None) == rta.RTA_E_ARG
+    assert lib.rta_process_device(None, None, None, None) == rta.RTA_E_ARG
+    assert lib.rta_reset(None) == rta.RTA_E_ARG
+    assert lib.rta_query(None, None) == rta.RTA_E_ARG
+    assert lib.rta_create(None, 48000.0, 128, None, 1, 1, None, None, 0, 0) == rta.RTA_E_ARG
+
+
+def _create_status(rta, fs=48000.0, block=128, scheme=None, n_in=1, n_out=1,
+                   lens=(256,), spectra=0, flags=0, null_filter=False):
+    taps = [np.ones(max(1, n), np.float32) for n in lens]
+    fp = ctypes.POINTER(ctypes.c_float)
+    ptrs = (fp * len(lens))(*[None if null_filter else t.ctypes.data_as(fp) for t in taps])
+    lengths = (ctypes.c_int64 * len(lens))(*lens)
+    sch = None
+    if scheme is not None:
+        sizes = (ctypes.c_int32 * len(scheme))(*[s for s, _ in scheme])
+        counts = (ctypes.c_int32 * len(scheme))(*[c for _, c in scheme])
+        sch = rta.rta_scheme(len(scheme), sizes, counts)
+    ctx = ctypes.c_void_p()
+    st = rta._lib.rta_create(ctypes.byref(ctx), fs, block,
+                             ctypes.byref(sch) if sch is not None else None,
+                             n_in, n_out, ptrs, lengths, spectra, flags)
+    assert not ctx.value
+    return st
+
+
+@pytest.mark.parametrize("kw", [
+    dict(fs=0.0), dict(fs=float("nan")), dict(block=100), dict(block=8),
+    dict(block=8192), dict(n_in=0), dict(n_out=0, lens=()), dict(spectra=7),
+    dict(flags=0x100), dict(lens=(-1,)), dict(null_filter=True),
+    # schemes: first tier must equal the block, sizes increasing powers of two
+    dict(scheme=[(256, 4)]), dict(scheme=[(128, 4), (128, 0)]),
+    dict(scheme=[(128, 4), (384, 0)]), dict(scheme=[(128, 0), (1024, 0)]),
+    # later tier must start at least 2*size - block into the filter
+    dict(scheme=[(128, 4), (1024, 0)]),
+    # a scheme that does not cover the filter
+    dict(scheme=[(128, 1)], lens=(1000,)),
+])
+def test_invalid_arguments_are_rejected_before_any_device_call(rta, kw):
+    assert _create_status(rta, **kw) == rta.RTA_E_ARG
+
+
+def test_table1_buffer_latency_matches_block_over_fs(rta):
+    path = os.path.join(ROOT, "tests", "golden", "table1_buffer_latency.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    assert len(rows) == 9
+    for block, ms in rows:
+        assert round(rta.deadline_us(int(block), 48000.0) / 1000.0, 2) == float(ms)

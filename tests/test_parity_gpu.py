@@ -1,0 +1,234 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerance: relative RMS error per output channel <= -100 dB for FP32 spectra
+(1e-5), <= -60 dB for FP16 and <= -45 dB for BF16 spectra.  Small cases are
+compared sample by sample over the whole output including the filter tail;
+the full-size 1 -> 32 x 480,000-tap case is compared at sampled outputs that
+the oracle evaluates one by one.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2509_04390_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+FP32_DB, FP16_DB, BF16_DB = -100.0, -60.0, -45.0
+
+
+@pytest.fixture(scope="module")
+def rta():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    from paper_2509_04390_amd import rta as mod
+    return mod
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+class env:
+    """Temporarily set tuning environment variables read at rta_create."""
+
+    def __init__(self, **kw):
+        self.kw = {k: str(v) for k, v in kw.items()}
+
+    def __enter__(self):
+        self.old = {k: os.environ.get(k) for k in self.kw}
+        os.environ.update(self.kw)
+
+    def __exit__(self, *a):
+        for k, v in self.old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+def make_filters(seed, lens, rt60=0.3):
+    Q, L = len(lens), len(lens[0])
+    filt = []
+    for q in range(Q):
+        row = []
+        for l in range(L):
+            n = lens[q][l]
+            f = workloads.reverb_filters(seed * 1000 + q * L + l, 1, 1, max(n, 1), rt60)[0][0]
+            row.append(f[:n] if n else None)
+        filt.append(row)
+    return filt
+
+
+def padded_signal(seed, Q, n_blocks, B, max_len):
+    x = workloads.white_noise(seed, Q, n_blocks * B)
+    flush = -(-max(max_len - 1, 0) // B) * B
+    return np.concatenate([x, np.zeros((Q, flush), np.float32)], axis=1)
+
+
+def check_db(y, ref, limit, what):
+    live = np.sum(ref ** 2, axis=1) > 0
+    assert np.all(y[~live] == 0.0), f"{what}: outputs without a path must be zero"
+    err = oracle.error_db(y[live], ref[live])
+    say(f"  {what}: max error {err.max():.1f} dB over {live.sum()} outputs")
+    assert np.all(err <= limit), f"{what}: {err} dB > {limit} dB"
+    return err
+
+
+CASES = [
+    # (B, lens[q][l], streamed blocks)
+    (16, [[1]], 6),
+    (16, [[16]], 6),
+    (16, [[17]], 6),
+    (16, [[300, 0], [0, 77]], 20),
+    (64, [[1000, 64, 0], [129, 700, 1]], 24),
+    (128, [[5000, 128 * 7, 3], [1, 0, 4000], [2500, 130, 129]], 30),
+    (256, [[65536 // 8, 256 * 20 + 1]], 12),
+    (1024, [[10000], [3000]], 10),     # two bin slices per row
+    (4096, [[20000, 9000]], 6),        # eight bin slices, 64 KB of LDS
+]
+
+
+@pytest.mark.parametrize("G", [1, 2, 4])
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_upols_fp32_matches_oracle_full_length(rta, case, G):
+    B, lens, nb = CASES[case]
+    Q, L = len(lens), len(lens[0])
+    filt = make_filters(case + 1, lens)
+    maxlen = max(max(r) for r in lens)
+    x = padded_signal(case + 50, Q, nb, B, maxlen)
+    say(f"case {case}: B={B} Q={Q} L={L} lens={lens} G={G} samples={x.shape[1]}")
+    with env(RTA_G=G, RTA_ROWS=3):
+        with rta.Convolver(filt, B) as cv:
+            y = cv.run(x)
+    ref = oracle.direct(x, filt, 0, x.shape[1])
+    check_db(y, ref, FP32_DB, f"B={B} G={G}")
+
+
+def test_device_path_equals_host_path_and_reruns_are_bitwise(rta):
+    B, lens, nb = CASES[5]
+    filt = make_filters(77, lens)
+    x = padded_signal(78, len(lens), nb, B, 5000)
+    with env(RTA_ROWS=4):
+        with rta.Convolver(filt, B) as cv:
+            say("host path")
+            y1 = cv.run(x)
+            cv.reset()
+            say("device path")
+            y2 = cv.run_device(x)
+            cv.reset()
+            y3 = cv.run(x)
+            assert cv.info()["blocks_done"] == x.shape[1] // B
+    assert np.array_equal(y1, y2)
+    assert np.array_equal(y1, y3)
+
+
+def test_eager_launches_equal_graph_replays(rta):
+    B, lens, nb = CASES[4]
+    filt = make_filters(5, lens)
+    x = padded_signal(6, len(lens), nb, B, 1000)
+    with rta.Convolver(filt, B) as cv:
+        y_graph = cv.run(x)
+    with rta.Convolver(filt, B, flags=rta.RTA_FLAG_NO_GRAPH) as cv:
+        y_eager = cv.run(x)
+    assert np.array_equal(y_graph, y_eager)
+
+
+def test_block_shift_is_bitwise_invariant(rta):
+    B = 64
+    lens = [[3000, 200]]
+    filt = make_filters(9, lens)
+    x = padded_signal(10, 1, 20, B, 3000)
+    xs = np.concatenate([np.zeros((1, B), np.float32), x], axis=1)
+    with rta.Convolver(filt, B) as cv:
+        y = cv.run(x)
+        cv.reset()
+        ys = cv.run(xs)
+    assert np.all(ys[:, :B] == 0.0)
+    assert np.array_equal(ys[:, B:], y)
+
+
+def test_impulse_returns_the_filters(rta):
+    B = 128
+    lens = [[4000, 129, 128]]
+    filt = make_filters(11, lens)
+    x = np.zeros((1, 4096), np.float32)
+    x[0, 0] = 1.0
+    with rta.Convolver(filt, B) as cv:
+        y = cv.run(x)
+    ref = np.zeros((3, 4096))
+    for l in range(3):
+        ref[l, :lens[0][l]] = filt[0][l]
+    check_db(y, ref, FP32_DB, "impulse")
+
+
+def test_delta_filters_at_partition_boundaries(rta):
+    B = 64
+    delays = [0, 1, B - 1, B, B + 1, 5 * B - 1, 5 * B]
+    filt = [[np.eye(1, d + 1, d, dtype=np.float32)[0] for d in delays]]
+    x = padded_signal(12, 1, 12, B, max(delays) + 1)
+    with rta.Convolver(filt, B) as cv:
+        y = cv.run(x)
+    ref = np.zeros((len(delays), x.shape[1]))
+    for l, d in enumerate(delays):
+        ref[l, d:] = x[0, :x.shape[1] - d]
+    check_db(y, ref, FP32_DB, "delta filters")
+
+
+@pytest.mark.parametrize("spectra,limit", [("fp16", FP16_DB), ("bf16", BF16_DB)])
+def test_reduced_precision_spectra(rta, spectra, limit):
+    wl = workloads.config("small")
+    filt = wl.filters()
+    x = wl.signal_array(flush=True)
+    say(f"small config, {spectra} spectra, {x.shape[1]} samples")
+    with rta.Convolver(filt, wl.block, spectra=spectra) as cv:
+        y = cv.run_device(x)
+    ref = oracle.fftols(x, filt, x.shape[1])
+    check_db(y, ref, limit, spectra)
+
+
+def test_fp16_overflow_is_reported(rta):
+    big = [[np.full(256, 1000.0, np.float32)]]   # DC bin = 256000 > 65504
+    with pytest.raises(rta.RtaError) as e:
+        rta.Convolver(big, 256, spectra="fp16")
+    assert e.value.status == rta.RTA_E_RANGE
+    with rta.Convolver(big, 256, spectra="bf16"):
+        pass
+
+
+def test_small_config_fp32_streamed_and_tail(rta):
+    wl = workloads.config("small")
+    filt = wl.filters()
+    x = wl.signal_array(flush=True)
+    say(f"small config fp32: {x.shape[1]} samples")
+    with rta.Convolver(filt, wl.block) as cv:
+        y = cv.run(x)
+        info = cv.info()
+    assert info["tier_count"][0] == 65536 // 256
+    ref = oracle.fftols(x, filt, x.shape[1])
+    check_db(y, ref, FP32_DB, "small/fftols")
+    idx = np.unique(np.r_[0, 255, 256, 25599, 25600, 65535, 65536, x.shape[1] - 1,
+                          np.random.default_rng(0).integers(0, x.shape[1], 500)])
+    refd = oracle.direct_at(x, filt, idx)
+    check_db(y[:, idx], refd, FP32_DB, "small/direct")
+
+
+def test_main_config_full_size_sampled(rta):
+    """1 input -> 32 outputs, 480,000-tap filters, block 128, 2,000 blocks."""
+    wl = workloads.config("main")
+    filt = wl.filters()
+    x = wl.signal_array()
+    say(f"main config: Q={wl.n_in} L={wl.n_out} taps={wl.lengths} blocks={wl.n_blocks}")
+    with rta.Convolver(filt, wl.block) as cv:
+        info = cv.info()
+        assert info["tier_count"][0] == 3750
+        y = cv.run_device(x)
+    rng = np.random.default_rng(2)
+    n = x.shape[1]
+    idx = np.unique(np.r_[0, 1, 127, 128, n - 1, n - 128, rng.integers(0, n, 200)])
+    ref = oracle.direct_at(x, filt, idx)
+    check_db(y[:, idx], ref, FP32_DB, "main/direct")
