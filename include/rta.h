@@ -136,7 +136,7 @@ int rta_process(rta_ctx* ctx, const float* in, float* out);
 
 /* Process one block, device memory in and out, stream-ordered.
  *   d_in    [n_in][block] FP32 device array; d_out [n_out][block] FP32.
- *   stream  hipStream_t to launch on (NULL: the context's own stream).
+ *   stream  hipStream_t to launch on; NULL is HIP's null (default) stream.
  * Enqueues the block and returns without waiting; d_out is valid once the
  * stream reaches this point.  Successive calls must be ordered on one
  * stream (the block index lives in device memory and advances per call). */
@@ -150,6 +150,18 @@ int rta_reset(rta_ctx* ctx);
 /* Fill *info with the context's geometry and counters.  Synchronizes the
  * context's stream to read the block index. */
 int rta_query(rta_ctx* ctx, rta_info* info);
+
+/* Kernel timing (profiling aid).  After rta_timing_enable(ctx, 1), every
+ * block launched by rta_process_device() or by rta_process() with
+ * RTA_FLAG_NO_GRAPH records three HIP events on its launch stream: before the
+ * multiply-accumulate kernel, between it and the output kernel, and after the
+ * output kernel.  rta_timing_read() waits for the recorded events and returns
+ * the number of timed blocks and the summed durations in milliseconds of the
+ * two kernels, then forgets them.  Event pairs beyond 65536 blocks are not
+ * recorded.  rta_timing_enable(ctx, 0) stops recording. */
+int rta_timing_enable(rta_ctx* ctx, int32_t on);
+int rta_timing_read(rta_ctx* ctx, int64_t* blocks, double* mac_ms,
+                    double* final_ms);
 
 /* Release the context and all its memory.  NULL is accepted (no-op). */
 int rta_destroy(rta_ctx* ctx);

@@ -1,22 +1,25 @@
 // kernels.hpp -- gfx950 kernels of the partitioned convolution.
 //
-// k_block: one launch per audio block.  Workgroup i runs work item i of the
-// block's phase list.  Items of kind MAC0 cover the uniform first tier
-// (partition = block, Sec. IV): an item owns a group of G outputs, one
-// input q, a partition range [p0, p1) and a slice of bins, and computes
+// Two launches per audio block, ordered on one stream.
+//
+// k_mac: workgroup i runs work item i of the block's phase list.  Items of
+// kind MAC0 cover the uniform first tier (partition = block, Sec. IV): an
+// item owns a group of G outputs, one input q, a partition range [p0, p1) and
+// a slice of bins, and computes
 //     Y_l[k] += sum_{p in [p0,p1)} H_{l,q,p}[k] * X_q[(n - p) mod K][k]
 // (Sec. IV step 2, frequency-domain delay line as a ring with a head index).
 // Items whose range starts at p = 0 transform the current input window
-// themselves (Sec. IV step 1: last 2B samples, real FFT) so no second launch
-// is needed; one of them stores that spectrum into the ring slot n mod K for
-// later blocks.  Each item writes its partial sums to its own slot; the last
-// item of a group to finish (an atomic arrival count, no waiting) adds the
-// slots in a fixed order, runs the inverse real FFT and keeps the second
-// half of the 2B samples (overlap-save, Sec. IV step 3).
+// themselves (Sec. IV step 1: last 2B samples, real FFT), so no launch is
+// spent on the forward transform; one of them stores that spectrum into the
+// ring slot n mod K for later blocks.  Each item writes its partial sums to
+// its own slot.
 //
-// The block index lives in device memory: every workgroup reads it first and
-// the last workgroup to read it advances it, so identical launches (and graph
-// replays) process successive blocks.
+// k_final: one workgroup per output group adds the group's slots in a fixed
+// order, runs the inverse real FFT and keeps the second half of the 2B
+// samples (overlap-save, Sec. IV step 3).
+//
+// The block index lives in device memory and k_final advances it, so
+// identical launches (and graph replays) process successive blocks.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -75,7 +78,6 @@ struct KArgs {
   const Item* items;         // [n_phase][max_items]
   const int32_t* phase_count;
   const Group* groups;
-  uint32_t* gcount;          // per-group arrival counters (zero between blocks)
   DevState* state;
   float* hist;               // input history [Q][hist_len]
   const float* in;           // [Q][B]
@@ -91,9 +93,7 @@ struct KArgs {
 // ---------------------------------------------------------------------------
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 
-struct bf16_t { uint16_t bits; };
 struct f16c_t { uint32_t bits; };   // packed (re, im) FP16 pair
 struct bf16c_t { uint32_t bits; };  // packed (re, im) BF16 pair
 
@@ -112,10 +112,15 @@ template <> struct HVec<f16c_t> {
   static constexpr int C = 4;
   static __device__ __forceinline__ void load(const f16c_t* p, float2 (&h)[C]) {
     const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
+    // Each 32-bit word is one (re, im) pair.  The halves are taken apart as
+    // scalars: a vector bit_cast of v[j] here makes the compiler drop three
+    // of the four words of the load.
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const f16x2 t = __builtin_bit_cast(f16x2, v[j]);
-      h[j] = make_float2((float)t.x, (float)t.y);
+      const uint32_t w = v[j];
+      const _Float16 re = __builtin_bit_cast(_Float16, (uint16_t)(w & 0xffffu));
+      const _Float16 im = __builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
+      h[j] = make_float2((float)re, (float)im);
     }
   }
 };
@@ -355,26 +360,10 @@ __device__ void first_tier_final(const KArgs& A, const DevTier& T, const Group& 
 }
 
 template <typename HT, int G>
-__global__ __launch_bounds__(kThreads) void k_block(const KArgs A) {
+__global__ __launch_bounds__(kThreads) void k_mac(const KArgs A) {
   extern __shared__ float2 lds[];
-  __shared__ int64_t sh_n;
-  __shared__ int sh_last;
   const int tid = threadIdx.x;
-
-  if (tid == 0) sh_n = __hip_atomic_load(&A.state->block, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __syncthreads();
-  const int64_t n = sh_n;
-  if (tid == 0) {
-    // The block index has been read (it is in LDS): count this workgroup;
-    // the last one of the launch advances the index for the next launch.
-    const uint32_t old = __hip_atomic_fetch_add(&A.state->arrive, 1u, __ATOMIC_RELEASE,
-                                                __HIP_MEMORY_SCOPE_AGENT);
-    if (old == gridDim.x - 1) {
-      A.state->arrive = 0;
-      A.state->block = n + 1;
-    }
-  }
-
+  const int64_t n = A.state->block;  // advanced only by k_final of the previous block
   const int phase = (int)(n % A.n_phase);
   if ((int)blockIdx.x >= A.phase_count[phase]) return;
   const Item it = A.items[(int64_t)phase * A.max_items + blockIdx.x];
@@ -404,21 +393,30 @@ __global__ __launch_bounds__(kThreads) void k_block(const KArgs A) {
     }
     mac_item<HT, G>(A, T, it, grp, n, x0, lds);
   }
+}
 
-  // arrival: the last item of the group finishes the block for its outputs
-  __threadfence();
+// One workgroup per output group: reduce the group's partial slots, inverse
+// FFT, overlap-save output.  Runs after k_mac of the same block on the same
+// stream, so every partial is visible without in-kernel fences.  The last
+// workgroup to read the block index advances it for the next block.
+template <int G>
+__global__ __launch_bounds__(kThreads) void k_final(const KArgs A) {
+  extern __shared__ float2 lds[];
+  __shared__ int64_t sh_n;
+  if (threadIdx.x == 0) sh_n = A.state->block;
   __syncthreads();
-  if (tid == 0) {
-    const uint32_t old = __hip_atomic_fetch_add(&A.gcount[it.group], 1u, __ATOMIC_ACQ_REL,
+  const int64_t n = sh_n;
+  if (threadIdx.x == 0) {
+    const uint32_t old = __hip_atomic_fetch_add(&A.state->arrive, 1u, __ATOMIC_RELAXED,
                                                 __HIP_MEMORY_SCOPE_AGENT);
-    sh_last = (old == (uint32_t)it.target - 1u);
+    if (old == gridDim.x - 1) {  // every workgroup has read n
+      A.state->arrive = 0;
+      A.state->block = n + 1;
+    }
   }
-  __syncthreads();
-  if (!sh_last) return;
-  __threadfence();
-
-  if (it.kind == K_MAC0) first_tier_final<G>(A, T, grp, n, bufA, bufB);
-  if (tid == 0) A.gcount[it.group] = 0;
+  const DevTier& T = A.tier[0];
+  const Group grp = A.groups[blockIdx.x];
+  first_tier_final<G>(A, T, grp, n, lds, lds + T.P);
 }
 
 // ---------------------------------------------------------------------------
@@ -437,10 +435,10 @@ __device__ __forceinline__ void store_bin(float2* H, int64_t i, float2 v, int*) 
 
 __device__ __forceinline__ void store_bin(f16c_t* H, int64_t i, float2 v, int* range) {
   if (fabsf(v.x) > 65504.f || fabsf(v.y) > 65504.f || v.x != v.x || v.y != v.y) atomicOr(range, 1);
-  f16x2 t;
-  t.x = (_Float16)v.x;  // round to nearest even
-  t.y = (_Float16)v.y;
-  H[i].bits = __builtin_bit_cast(uint32_t, t);
+  const _Float16 re = (_Float16)v.x;  // round to nearest even
+  const _Float16 im = (_Float16)v.y;
+  H[i].bits = (uint32_t)__builtin_bit_cast(uint16_t, re) |
+              ((uint32_t)__builtin_bit_cast(uint16_t, im) << 16);
 }
 
 __device__ __forceinline__ uint32_t bf16_rne(float f) {

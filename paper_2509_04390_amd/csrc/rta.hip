@@ -74,13 +74,13 @@ struct rta_ctx {
   TierHost tier[kMaxTiers];
   int G = 1, rows_per_item = 0, grid = 0, n_phase = 1, max_items = 0;
   int64_t hist_len = 0, ring_len = 0;
-  size_t lds_bytes = 0;
+  size_t lds_bytes = 0;        // k_mac dynamic LDS
+  size_t lds_final_bytes = 0;  // k_final dynamic LDS
 
   float* hist = nullptr;
   Item* items = nullptr;
   int32_t* phase_count = nullptr;
   Group* groups = nullptr;
-  uint32_t* gcount = nullptr;
   DevState* state = nullptr;
   int n_groups = 0;
 
@@ -92,6 +92,9 @@ struct rta_ctx {
   hipGraphExec_t gexec = nullptr;
 
   bool poisoned = false;
+  bool timing = false;
+  std::vector<hipEvent_t> events;  // 3 per timed block
+  size_t events_used = 0;
   int64_t device_bytes = 0, spectra_bytes = 0;
   double h_bytes = 0, x_bytes = 0, io_bytes = 0, cmacs = 0;
   std::vector<void*> dev_allocs;
@@ -145,14 +148,13 @@ std::vector<float2> twiddles(int P) {
 }
 
 using BlockKernel = void (*)(const KArgs);
-using SpecKernel = void (*)(const float*, const SpecRow*, void*, int, int, const float2*, int*);
 
-BlockKernel block_kernel(int dtype, int G) {
+BlockKernel mac_kernel(int dtype, int G) {
 #define RTA_PICK(HT)                                   \
   switch (G) {                                         \
-    case 1: return k_block<HT, 1>;                     \
-    case 2: return k_block<HT, 2>;                     \
-    case 4: return k_block<HT, 4>;                     \
+    case 1: return k_mac<HT, 1>;                       \
+    case 2: return k_mac<HT, 2>;                       \
+    case 4: return k_mac<HT, 4>;                       \
     default: return nullptr;                           \
   }
   if (dtype == RTA_FP32) RTA_PICK(float2)
@@ -160,6 +162,15 @@ BlockKernel block_kernel(int dtype, int G) {
   if (dtype == RTA_BF16) RTA_PICK(bf16c_t)
 #undef RTA_PICK
   return nullptr;
+}
+
+BlockKernel final_kernel(int G) {
+  switch (G) {
+    case 1: return k_final<1>;
+    case 2: return k_final<2>;
+    case 4: return k_final<4>;
+    default: return nullptr;
+  }
 }
 
 int vec_bins(int dtype) { return dtype == RTA_FP32 ? 2 : 4; }
@@ -384,7 +395,6 @@ KArgs make_args(const rta_ctx* c, const float* in, float* out) {
   a.items = c->items;
   a.phase_count = c->phase_count;
   a.groups = c->groups;
-  a.gcount = c->gcount;
   a.state = c->state;
   a.hist = c->hist;
   a.in = in;
@@ -400,10 +410,33 @@ KArgs make_args(const rta_ctx* c, const float* in, float* out) {
   return a;
 }
 
-int launch_block(rta_ctx* c, const float* in, float* out, hipStream_t s) {
-  BlockKernel k = block_kernel(c->dtype, c->G);
+// The two launches of one block, in stream order.
+void enqueue_block(const rta_ctx* c, const float* in, float* out, hipStream_t s) {
   const KArgs a = make_args(c, in, out);
-  hipLaunchKernelGGL(k, dim3(c->grid), dim3(kThreads), c->lds_bytes, s, a);
+  hipLaunchKernelGGL(mac_kernel(c->dtype, c->G), dim3(c->grid), dim3(kThreads), c->lds_bytes, s, a);
+  hipLaunchKernelGGL(final_kernel(c->G), dim3(c->n_groups), dim3(kThreads), c->lds_final_bytes, s, a);
+}
+
+constexpr size_t kMaxTimedBlocks = 65536;
+
+int launch_block(rta_ctx* c, const float* in, float* out, hipStream_t s) {
+  if (c->timing && c->events_used + 3 <= 3 * kMaxTimedBlocks) {
+    while (c->events.size() < c->events_used + 3) {
+      hipEvent_t e;
+      HIP_TRY(c, hipEventCreate(&e));
+      c->events.push_back(e);
+    }
+    hipEvent_t* e = &c->events[c->events_used];
+    c->events_used += 3;
+    const KArgs a = make_args(c, in, out);
+    HIP_TRY(c, hipEventRecord(e[0], s));
+    hipLaunchKernelGGL(mac_kernel(c->dtype, c->G), dim3(c->grid), dim3(kThreads), c->lds_bytes, s, a);
+    HIP_TRY(c, hipEventRecord(e[1], s));
+    hipLaunchKernelGGL(final_kernel(c->G), dim3(c->n_groups), dim3(kThreads), c->lds_final_bytes, s, a);
+    HIP_TRY(c, hipEventRecord(e[2], s));
+  } else {
+    enqueue_block(c, in, out, s);
+  }
   HIP_TRY(c, hipGetLastError());
   return RTA_OK;
 }
@@ -417,8 +450,6 @@ int zero_state(rta_ctx* c) {
   }
   HIP_TRY(c, hipMemsetAsync(c->hist, 0, sizeof(float) * (size_t)c->Q * c->hist_len, c->stream));
   HIP_TRY(c, hipMemsetAsync(c->state, 0, sizeof(DevState), c->stream));
-  HIP_TRY(c, hipMemsetAsync(c->gcount, 0, sizeof(uint32_t) * (size_t)std::max(1, c->n_groups),
-                            c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return RTA_OK;
 }
@@ -571,7 +602,6 @@ int create_impl(rta_ctx* c, const std::vector<int>& size, const std::vector<int>
   if ((st = dev_alloc(c, &c->items, (size_t)c->max_items)) != RTA_OK) return st;
   if ((st = dev_alloc(c, &c->phase_count, 1)) != RTA_OK) return st;
   if ((st = dev_alloc(c, &c->groups, groups.size())) != RTA_OK) return st;
-  if ((st = dev_alloc(c, &c->gcount, groups.size())) != RTA_OK) return st;
   if ((st = dev_alloc(c, &c->state, 1)) != RTA_OK) return st;
   if (!flat.empty())
     HIP_TRY(c, hipMemcpy(c->items, flat.data(), sizeof(Item) * flat.size(), hipMemcpyHostToDevice));
@@ -596,19 +626,25 @@ int create_impl(rta_ctx* c, const std::vector<int>& size, const std::vector<int>
   for (int t = 0; t < c->n_tiers; ++t) lds = std::max(lds, sizeof(float2) * 2 * (size_t)c->tier[t].P);
   lds = std::max(lds, sizeof(float2) * (size_t)kThreads * C * c->G);
   c->lds_bytes = lds;
+  c->lds_final_bytes = sizeof(float2) * 2 * (size_t)c->tier[0].P;
   int max_lds = 0;
   HIP_TRY(c, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
-  if ((int64_t)lds + 64 > (int64_t)max_lds) return RTA_E_UNSUPPORTED;
-  if (lds > 65536) {
-    BlockKernel k = block_kernel(c->dtype, c->G);
-    HIP_TRY(c, hipFuncSetAttribute(reinterpret_cast<const void*>(k),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  }
+  if ((int64_t)std::max(c->lds_bytes, c->lds_final_bytes) + 64 > (int64_t)max_lds)
+    return RTA_E_UNSUPPORTED;
+  if (c->lds_bytes > 65536)
+    HIP_TRY(c, hipFuncSetAttribute(reinterpret_cast<const void*>(mac_kernel(c->dtype, c->G)),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_bytes));
+  if (c->lds_final_bytes > 65536)
+    HIP_TRY(c, hipFuncSetAttribute(reinterpret_cast<const void*>(final_kernel(c->G)),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)c->lds_final_bytes));
 
   return zero_state(c);
 }
 
 void free_all(rta_ctx* c) {
+  for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+  c->events.clear();
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
@@ -623,9 +659,7 @@ int capture_graph(rta_ctx* c) {
   HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
   (void)hipMemcpyAsync(c->d_in, c->h_in, sizeof(float) * (size_t)c->Q * c->B,
                        hipMemcpyHostToDevice, c->stream);
-  BlockKernel k = block_kernel(c->dtype, c->G);
-  const KArgs a = make_args(c, c->d_in, c->d_out);
-  hipLaunchKernelGGL(k, dim3(c->grid), dim3(kThreads), c->lds_bytes, c->stream, a);
+  enqueue_block(c, c->d_in, c->d_out, c->stream);
   (void)hipMemcpyAsync(c->h_out, c->d_out, sizeof(float) * (size_t)c->L * c->B,
                        hipMemcpyDeviceToHost, c->stream);
   HIP_TRY(c, hipStreamEndCapture(c->stream, &c->graph));
@@ -657,6 +691,7 @@ int rta_create(rta_ctx** out, double fs, int32_t block, const rta_scheme* scheme
   if (c->G != 1 && c->G != 2 && c->G != 4) c->G = 1;
   c->rows_per_item = env_int("RTA_ROWS", 0);
   st = create_impl(c, size, count, filters, lengths);
+  if (st == RTA_OK && !(flags & RTA_FLAG_NO_GRAPH)) st = capture_graph(c);
   if (st != RTA_OK) {
     free_all(c);
     delete c;
@@ -678,10 +713,7 @@ int rta_process(rta_ctx* c, const float* in, float* out) {
     HIP_TRY(c, hipMemcpyAsync(c->h_out, c->d_out, sizeof(float) * (size_t)c->L * c->B,
                               hipMemcpyDeviceToHost, c->stream));
   } else {
-    if (c->gexec == nullptr) {
-      int st = capture_graph(c);
-      if (st != RTA_OK) return st;
-    }
+    if (c->gexec == nullptr) return RTA_E_STATE;
     HIP_TRY(c, hipGraphLaunch(c->gexec, c->stream));
   }
   HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -692,8 +724,7 @@ int rta_process(rta_ctx* c, const float* in, float* out) {
 int rta_process_device(rta_ctx* c, const float* d_in, float* d_out, void* stream) {
   if (c == nullptr || d_in == nullptr || d_out == nullptr) return RTA_E_ARG;
   if (c->poisoned) return RTA_E_DEVICE;
-  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
-  return launch_block(c, d_in, d_out, s);
+  return launch_block(c, d_in, d_out, static_cast<hipStream_t>(stream));
 }
 
 int rta_reset(rta_ctx* c) {
@@ -734,6 +765,30 @@ int rta_query(rta_ctx* c, rta_info* info) {
   DevState s{};
   HIP_TRY(c, hipMemcpy(&s, c->state, sizeof(s), hipMemcpyDeviceToHost));
   info->blocks_done = s.block;
+  return RTA_OK;
+}
+
+int rta_timing_enable(rta_ctx* c, int32_t on) {
+  if (c == nullptr) return RTA_E_ARG;
+  c->timing = on != 0;
+  return RTA_OK;
+}
+
+int rta_timing_read(rta_ctx* c, int64_t* blocks, double* mac_ms, double* final_ms) {
+  if (c == nullptr || blocks == nullptr || mac_ms == nullptr || final_ms == nullptr) return RTA_E_ARG;
+  if (c->poisoned) return RTA_E_DEVICE;
+  *blocks = 0;
+  *mac_ms = *final_ms = 0.0;
+  for (size_t i = 0; i + 3 <= c->events_used; i += 3) {
+    float a = 0.f, b = 0.f;
+    HIP_TRY(c, hipEventSynchronize(c->events[i + 2]));
+    HIP_TRY(c, hipEventElapsedTime(&a, c->events[i], c->events[i + 1]));
+    HIP_TRY(c, hipEventElapsedTime(&b, c->events[i + 1], c->events[i + 2]));
+    *mac_ms += a;
+    *final_ms += b;
+    *blocks += 1;
+  }
+  c->events_used = 0;
   return RTA_OK;
 }
 

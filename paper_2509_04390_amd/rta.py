@@ -34,7 +34,8 @@ RTA_FLAG_NO_GRAPH = 0x2
 RTA_MAX_TIERS = 8
 
 EXPORTED = ("rta_create", "rta_process", "rta_process_device", "rta_reset",
-            "rta_query", "rta_destroy", "rta_strerror")
+            "rta_query", "rta_timing_enable", "rta_timing_read", "rta_destroy",
+            "rta_strerror")
 
 
 class rta_scheme(ctypes.Structure):
@@ -76,10 +77,13 @@ _lib.rta_process_device.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_v
 _lib.rta_reset.argtypes = [ctypes.c_void_p]
 _lib.rta_query.argtypes = [ctypes.c_void_p, ctypes.POINTER(rta_info)]
 _lib.rta_destroy.argtypes = [ctypes.c_void_p]
+_lib.rta_timing_enable.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+_lib.rta_timing_read.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
 _lib.rta_strerror.argtypes = [ctypes.c_int]
 _lib.rta_strerror.restype = ctypes.c_char_p
 for _f in ("rta_create", "rta_process", "rta_process_device", "rta_reset", "rta_query",
-           "rta_destroy"):
+           "rta_timing_enable", "rta_timing_read", "rta_destroy"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -168,6 +172,20 @@ def rta_query(ctx) -> dict:
         v = getattr(info, name)
         d[name] = list(v)[:info.n_tiers] if hasattr(v, "__len__") else v
     return d
+
+
+def rta_timing_enable(ctx, on: bool) -> None:
+    _check(_lib.rta_timing_enable(ctx, 1 if on else 0), "rta_timing_enable")
+
+
+def rta_timing_read(ctx):
+    """(blocks, mac_ms_total, final_ms_total) since the last read."""
+    n = ctypes.c_int64()
+    a = ctypes.c_double()
+    b = ctypes.c_double()
+    _check(_lib.rta_timing_read(ctx, ctypes.byref(n), ctypes.byref(a), ctypes.byref(b)),
+           "rta_timing_read")
+    return n.value, a.value, b.value
 
 
 def rta_destroy(ctx) -> None:
