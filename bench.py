@@ -89,13 +89,14 @@ def cpu_baseline(wl, filt, x, max_channels: int):
 
 
 def copy_probe(mb: int, reps: int) -> None:
-    """Plain device copy of a known size, for scaling the memory counters."""
+    """A plain copy kernel of known size (elementwise negation into a second
+    buffer: reads and writes mb MiB each), for scaling the memory counters."""
     import torch
     n = mb * (1 << 20) // 4
     src = torch.ones(n, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(reps):
-        dst.copy_(src)
+        torch.neg(src, out=dst)
     torch.cuda.synchronize()
     print(json.dumps({"copy_probe_bytes": n * 4, "reps": reps}))
 
