@@ -11,9 +11,11 @@ Printed on one JSON line:
                 the timed steps, device-resident blocks launched back to back;
   rtf           its inverse (processing time / audio time, < 1 is real time);
   latency       p50/p99/max of synchronous host-memory rta_process() calls
-                (PCIe copies included) against the block deadline B/fs;
-  roofline      algorithmic bytes per launch of the block kernel / its mean
-                duration from HIP events on the launch stream, vs 8 TB/s;
+                (PCIe copies included) issued one every B/fs as an audio
+                callback would, against the deadline B/fs; also back to back;
+  roofline      algorithmic bytes per launch of the multiply-accumulate
+                kernel k_tail / its mean duration from HIP events on the
+                launch stream, vs 8 TB/s;
   cpu_baseline  the FP64 oracle (single-partition FFT overlap-save) timed on
                 the host cores over a bounded sample of the same workload.
 """
@@ -53,7 +55,7 @@ def kernel_source_hash() -> str:
 def measured_traffic(workload: str, spectra: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel sources; otherwise None."""
-    path = os.path.join(ROOT, "profiles", f"k_mac_{workload}_{spectra}_pmc.json")
+    path = os.path.join(ROOT, "profiles", f"k_tail_{workload}_{spectra}_pmc.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -88,6 +90,31 @@ def cpu_baseline(wl, filt, x, max_channels: int):
     }
 
 
+def read_probes(torch, rta, nbytes: int, grid: int, stream, reps: int = 20):
+    """Attainable streaming-read bandwidth of k_mac's load pattern, at the
+    spectra size (may be served partly by the 256 MB Infinity Cache) and at
+    1 GiB (larger than it)."""
+    out = {}
+    for tag, size in (("spectra_size", nbytes), ("1GiB", 1 << 30)):
+        buf = torch.ones(size // 4, dtype=torch.float32, device="cuda")
+        sink = torch.empty(grid, dtype=torch.float32, device="cuda")
+        for _ in range(3):
+            rta.rta_probe_read(buf.data_ptr(), size, grid, sink.data_ptr(), stream.cuda_stream)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        ms = []
+        for _ in range(reps):
+            e0.record(stream)
+            rta.rta_probe_read(buf.data_ptr(), size, grid, sink.data_ptr(), stream.cuda_stream)
+            e1.record(stream)
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        out[tag] = {"bytes": size, "grid": grid, "us_median": 1e3 * float(np.median(ms)),
+                    "gbs": size / (float(np.median(ms)) * 1e-3) / 1e9}
+        del buf, sink
+    return out
+
+
 def copy_probe(mb: int, reps: int) -> None:
     """A plain copy kernel of known size (elementwise negation into a second
     buffer: reads and writes mb MiB each), for scaling the memory counters."""
@@ -109,11 +136,13 @@ def main() -> int:
     ap.add_argument("--workload", default="main")
     ap.add_argument("--spectra", default="fp32", choices=["fp32", "fp16", "bf16"])
     ap.add_argument("--latency-blocks", type=int, default=2000)
-    ap.add_argument("--paced-blocks", type=int, default=0,
-                    help="also run this many host blocks paced every B/fs")
+    ap.add_argument("--paced-blocks", type=int, default=1000,
+                    help="host blocks issued one every B/fs (real-time pacing)")
     ap.add_argument("--cpu-channels", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mb", type=int, default=0)
+    ap.add_argument("--no-graph", action="store_true",
+                    help="rta_process launches eagerly instead of replaying a graph")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -145,7 +174,8 @@ def main() -> int:
     x = wl_steps.signal_array()
 
     t0 = time.perf_counter()
-    cv = rta.Convolver(filt, B, fs=fs, spectra=args.spectra)
+    cv = rta.Convolver(filt, B, fs=fs, spectra=args.spectra,
+                       flags=rta.RTA_FLAG_NO_GRAPH if args.no_graph else 0)
     info = cv.info()
     log(f"created in {time.perf_counter() - t0:.2f} s: grid={info['grid']} "
         f"rows/item={info['rows_per_item']} G={info['outputs_per_group']} "
@@ -159,13 +189,19 @@ def main() -> int:
         cv.process_device(xb[i], yb[i], stream)
     torch.cuda.synchronize()
 
-    # per-kernel HIP events recorded by the library on the launch stream
+    # per-kernel HIP events recorded by the library on the launch stream;
+    # device pointers are taken up front so the loop is one C call per block
+    pin = [xb[i].data_ptr() for i in range(nblk)]
+    pout = [yb[i].data_ptr() for i in range(nblk)]
+    sh = stream.cuda_stream
+    launch = rta._lib.rta_process_device
     rta.rta_timing_enable(cv.ctx, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
         i = args.warmup + k
-        cv.process_device(xb[i], yb[i], stream)
+        if launch(cv.ctx, pin[i], pout[i], sh) != 0:
+            raise RuntimeError("rta_process_device failed")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     n_timed, mac_ms, fin_ms = rta.rta_timing_read(cv.ctx)
@@ -175,8 +211,9 @@ def main() -> int:
     ms_per_step = 1e3 * wall / args.steps
     audio_per_step = B / fs
     value = audio_per_step / (ms_per_step / 1e3)
-    log(f"timed {args.steps} steps: {ms_per_step * 1e3:.1f} us/step; k_mac {mac_us:.1f} us, "
-        f"k_final {fin_us:.1f} us (mean of {n_timed})")
+    log(f"timed {args.steps} steps: {ms_per_step * 1e3:.1f} us/step; k_tail {mac_us:.1f} us, "
+        f"k_head {fin_us:.1f} us (mean of {n_timed})")
+    probes = read_probes(torch, rta, int(info["spectra_bytes"]), info["grid"], stream)
 
     # synchronous host-memory blocks: per-block latency including PCIe
     cv.reset()
@@ -203,11 +240,13 @@ def main() -> int:
             while time.perf_counter() < nxt:
                 pass
         plat_us = np.array(plat) * 1e6
-        paced = {"blocks": args.paced_blocks, "p50_us": float(np.percentile(plat_us, 50)),
+        paced = {"blocks": args.paced_blocks,
+                 "mode": "rta_process paced every B/fs, host memory, PCIe included",
+                 "p50_us": float(np.percentile(plat_us, 50)),
                  "p99_us": float(np.percentile(plat_us, 99)), "max_us": float(plat_us.max()),
                  "xruns": int(np.sum(plat_us > deadline))}
 
-    bytes_per_launch = info["h_bytes_per_block"] + info["x_bytes_per_block"] + Q * B * 4
+    bytes_per_launch = info["tail_bytes_per_block"]
     achieved = bytes_per_launch / (mac_us * 1e-6) / 1e9
     traffic = measured_traffic(wl.name, args.spectra)
     cpu = None
@@ -239,14 +278,15 @@ def main() -> int:
         "rtf": (ms_per_step / 1e3) / audio_per_step,
         "channel_filter_seconds_per_s": Q * L * (n_h / fs) * value,
         "deadline_us": deadline,
-        "latency": {"blocks": args.latency_blocks, "mode": "back-to-back, host memory, PCIe included",
-                    "p50_us": float(np.percentile(lat_us, 50)),
-                    "p99_us": float(np.percentile(lat_us, 99)),
-                    "max_us": float(lat_us.max()),
-                    "xruns": int(np.sum(lat_us > deadline))},
-        "latency_paced": paced,
+        "latency": paced,
+        "latency_back_to_back": {"blocks": args.latency_blocks,
+                                 "mode": "back-to-back rta_process, host memory, PCIe included",
+                                 "p50_us": float(np.percentile(lat_us, 50)),
+                                 "p99_us": float(np.percentile(lat_us, 99)),
+                                 "max_us": float(lat_us.max()),
+                                 "xruns": int(np.sum(lat_us > deadline))},
         "roofline": {
-            "kernel": "k_mac",
+            "kernel": "k_tail",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
@@ -255,8 +295,9 @@ def main() -> int:
             "traffic": traffic,
             "bytes_per_launch": bytes_per_launch,
             "kernel_us_mean": mac_us,
-            "final_kernel_us_mean": fin_us,
+            "head_kernel_us_mean": fin_us,
         },
+        "read_probe": probes,
         "cpu_baseline": cpu,
     }
     cv.close()

@@ -96,6 +96,10 @@ typedef struct rta_info {
                                      block, counted once per (q, slot)     */
     double  io_bytes_per_block;   /* input block + output block bytes      */
     double  cmacs_per_block;      /* complex multiply-accumulates / block  */
+    double  tail_bytes_per_block; /* algorithmic bytes of the multiply-
+                                     accumulate kernel (partitions >= 1):
+                                     their spectrum rows once plus their
+                                     delay-line slots once per input       */
     int32_t grid;                 /* workgroups per block launch           */
     int32_t outputs_per_group;    /* outputs sharing one input-spectrum
                                      load in the multiply-accumulate       */
@@ -128,10 +132,14 @@ int rta_create(rta_ctx** out, double fs, int32_t block,
 /* Process one block, host memory in and out, synchronously.
  *   in   [n_in][block] FP32 host array (row-major), read during the call.
  *   out  [n_out][block] FP32 host array, valid on return.
- * Copies the input block to the device, runs the block on the context's own
- * stream (a captured hipGraph unless RTA_FLAG_NO_GRAPH), copies the output
- * back and waits.  Must not be interleaved with rta_process_device() calls
- * that are still in flight on another stream. */
+ * The input is copied into the context's pinned, device-mapped buffer; the
+ * block's output kernel (a captured hipGraph unless RTA_FLAG_NO_GRAPH) reads
+ * it and writes the output block straight into a second pinned buffer over
+ * PCIe, with no DMA copies.  The call spins until that kernel has finished
+ * and copies the output to `out`; the multiply-accumulate of partitions >= 1
+ * for the next block is left running on the context's stream and the next
+ * call is ordered after it.  Must not be interleaved with
+ * rta_process_device() calls still in flight on another stream. */
 int rta_process(rta_ctx* ctx, const float* in, float* out);
 
 /* Process one block, device memory in and out, stream-ordered.
@@ -151,17 +159,32 @@ int rta_reset(rta_ctx* ctx);
  * context's stream to read the block index. */
 int rta_query(rta_ctx* ctx, rta_info* info);
 
-/* Kernel timing (profiling aid).  After rta_timing_enable(ctx, 1), every
- * block launched by rta_process_device() or by rta_process() with
- * RTA_FLAG_NO_GRAPH records three HIP events on its launch stream: before the
- * multiply-accumulate kernel, between it and the output kernel, and after the
- * output kernel.  rta_timing_read() waits for the recorded events and returns
- * the number of timed blocks and the summed durations in milliseconds of the
- * two kernels, then forgets them.  Event pairs beyond 65536 blocks are not
- * recorded.  rta_timing_enable(ctx, 0) stops recording. */
+/* Kernel timing (profiling aid).  Each block is two kernel launches: the
+ * output kernel of this block (forward FFT, partition 0, inverse FFT and
+ * overlap-save output) and the multiply-accumulate kernel of partitions >= 1
+ * for the next block.  After rta_timing_enable(ctx, 1), every block launched
+ * by rta_process_device() or by rta_process() with RTA_FLAG_NO_GRAPH records
+ * three HIP events on its launch stream: before the output kernel, between
+ * the two kernels and after the multiply-accumulate kernel.
+ * rta_timing_read() waits for the recorded events and returns the number of
+ * timed blocks and the summed durations in milliseconds of the
+ * multiply-accumulate kernel (mac_ms) and of the output kernel (final_ms),
+ * then forgets them.  Blocks beyond 65536 are not recorded.
+ * rta_timing_enable(ctx, 0) stops recording. */
 int rta_timing_enable(rta_ctx* ctx, int32_t on);
 int rta_timing_read(rta_ctx* ctx, int64_t* blocks, double* mac_ms,
                     double* final_ms);
+
+/* Measurement aid, independent of any context: launch a streaming-read
+ * kernel over the first floor(bytes/16)*16 bytes of device memory d_buf
+ * (16-byte aligned) with `grid` workgroups of 256 threads.  Workgroup w reads
+ * one contiguous chunk with the same 16-byte non-temporal loads as the
+ * multiply-accumulate kernel and writes one float to d_sink[w] (d_sink holds
+ * `grid` floats).  Stream-ordered on `stream` (NULL: HIP's null stream);
+ * time it with events to get the attainable read bandwidth of this access
+ * pattern.  Returns RTA_E_DEVICE if the launch fails. */
+int rta_probe_read(const void* d_buf, int64_t bytes, int32_t grid, float* d_sink,
+                   void* stream);
 
 /* Release the context and all its memory.  NULL is accepted (no-op). */
 int rta_destroy(rta_ctx* ctx);

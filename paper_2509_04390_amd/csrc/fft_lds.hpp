@@ -30,22 +30,27 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 }
 __device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
 
-// Complex FFT of length N = 2^logN held in LDS buffer `a`; `b` is LDS scratch
-// of the same length.  INV selects exp(+2 pi i/N) twiddles (unnormalized).
-// Every thread of the workgroup must call it; it returns the buffer that
-// holds the result and ends with a barrier.
+// Batched complex FFT: nb transforms of length N = 2^logN stored back to back
+// in LDS buffer `a` ([nb][N]); `b` is LDS scratch of the same size.  INV
+// selects exp(+2 pi i/N) twiddles (unnormalized).  Every thread of the
+// workgroup must call it; it returns the buffer that holds the results and
+// ends with a barrier.
 template <bool INV>
 __device__ float2* fft_stockham(float2* a, float2* b, int N, int logN,
-                                const float2* __restrict__ tw) {
+                                const float2* __restrict__ tw, int nb = 1) {
   const int tid = threadIdx.x, nt = blockDim.x;
   int Ns = 1, rem = logN;
   while (rem > 0) {
     if (rem >= 2) {
       const int quarter = N >> 2;
       const int ts = N / (Ns << 2);
-      for (int j = tid; j < quarter; j += nt) {
+      const int total = nb * quarter;
+      for (int w = tid; w < total; w += nt) {
+        const int bb = w >> (logN - 2), j = w & (quarter - 1);
+        const float2* ab = a + bb * N;
+        float2* bbuf = b + bb * N;
         const int k = j & (Ns - 1);
-        float2 v0 = a[j], v1 = a[j + quarter], v2 = a[j + 2 * quarter], v3 = a[j + 3 * quarter];
+        float2 v0 = ab[j], v1 = ab[j + quarter], v2 = ab[j + 2 * quarter], v3 = ab[j + 3 * quarter];
         if (Ns > 1) {
           float2 w1 = tw[k * ts], w2 = tw[2 * k * ts], w3 = tw[3 * k * ts];
           if (INV) { w1.y = -w1.y; w2.y = -w2.y; w3.y = -w3.y; }
@@ -56,27 +61,31 @@ __device__ float2* fft_stockham(float2* a, float2* b, int N, int logN,
         // forward: -i * d13 ; inverse: +i * d13
         const float2 jd = INV ? make_float2(-d13.y, d13.x) : make_float2(d13.y, -d13.x);
         const int base = ((j - k) << 2) + k;
-        b[base] = cadd(s02, s13);
-        b[base + Ns] = cadd(d02, jd);
-        b[base + 2 * Ns] = csub(s02, s13);
-        b[base + 3 * Ns] = csub(d02, jd);
+        bbuf[base] = cadd(s02, s13);
+        bbuf[base + Ns] = cadd(d02, jd);
+        bbuf[base + 2 * Ns] = csub(s02, s13);
+        bbuf[base + 3 * Ns] = csub(d02, jd);
       }
       Ns <<= 2;
       rem -= 2;
     } else {
       const int half = N >> 1;
       const int ts = N / (Ns << 1);
-      for (int j = tid; j < half; j += nt) {
+      const int total = nb * half;
+      for (int w = tid; w < total; w += nt) {
+        const int bb = w >> (logN - 1), j = w & (half - 1);
+        const float2* ab = a + bb * N;
+        float2* bbuf = b + bb * N;
         const int k = j & (Ns - 1);
-        float2 v0 = a[j], v1 = a[j + half];
+        float2 v0 = ab[j], v1 = ab[j + half];
         if (Ns > 1) {
           float2 w = tw[k * ts];
           if (INV) w.y = -w.y;
           v1 = cmul(v1, w);
         }
         const int base = ((j - k) << 1) + k;
-        b[base] = cadd(v0, v1);
-        b[base + Ns] = csub(v0, v1);
+        bbuf[base] = cadd(v0, v1);
+        bbuf[base + Ns] = csub(v0, v1);
       }
       Ns <<= 1;
       rem -= 1;
@@ -87,47 +96,55 @@ __device__ float2* fft_stockham(float2* a, float2* b, int N, int logN,
   return a;
 }
 
-// Packed spectrum of the 2P real samples whose complex FFT Z (length P) is in
-// `Z`; writes P packed bins to `X` (LDS or global, must not alias Z).
-// tw2 = W_2P^k table.  Ends with a barrier.
+// Packed spectra of nb real signals of 2P samples whose complex FFTs Z
+// (length P each, [nb][P]) are in `Z`; writes [nb][P] packed bins to `X`
+// (must not alias Z).  tw2 = W_2P^k table.  Ends with a barrier.
 __device__ __forceinline__ void rfft_post(const float2* Z, float2* X, int P,
-                                          const float2* __restrict__ tw2) {
-  for (int k = threadIdx.x; k <= (P >> 1); k += blockDim.x) {
+                                          const float2* __restrict__ tw2, int nb = 1) {
+  const int per = (P >> 1) + 1;
+  for (int w = threadIdx.x; w < nb * per; w += blockDim.x) {
+    const int bb = w / per, k = w - bb * per;
+    const float2* Zb = Z + bb * P;
+    float2* Xb = X + bb * P;
     if (k == 0) {
-      const float2 z = Z[0];
-      X[0] = make_float2(z.x + z.y, z.x - z.y);
+      const float2 z = Zb[0];
+      Xb[0] = make_float2(z.x + z.y, z.x - z.y);
       continue;
     }
-    const float2 zk = Z[k], zm = cconj(Z[P - k]);
+    const float2 zk = Zb[k], zm = cconj(Zb[P - k]);
     const float2 E = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y + zm.y));
     const float2 d = csub(zk, zm);
     const float2 O = make_float2(0.5f * d.y, -0.5f * d.x);  // -i d / 2
     const float2 wO = cmul(tw2[k], O);
-    X[k] = cadd(E, wO);
-    if (k != P - k) X[P - k] = cconj(csub(E, wO));
+    Xb[k] = cadd(E, wO);
+    if (k != P - k) Xb[P - k] = cconj(csub(E, wO));
   }
   __syncthreads();
 }
 
-// Inverse of rfft_post without the 1/2 factors: from packed bins X builds
-// Z' = 2 Z so that IFFT_P(Z') / (2P) = z, z[m] = w[2m] + i w[2m+1].
+// Inverse of rfft_post without the 1/2 factors, for nb spectra [nb][P]:
+// builds Z' = 2 Z so that IFFT_P(Z') / (2P) = z, z[m] = w[2m] + i w[2m+1].
 // Ends with a barrier.
 __device__ __forceinline__ void irfft_pre(const float2* X, float2* Z, int P,
-                                          const float2* __restrict__ tw2) {
-  for (int k = threadIdx.x; k <= (P >> 1); k += blockDim.x) {
+                                          const float2* __restrict__ tw2, int nb = 1) {
+  const int per = (P >> 1) + 1;
+  for (int w = threadIdx.x; w < nb * per; w += blockDim.x) {
+    const int bb = w / per, k = w - bb * per;
+    const float2* Xb = X + bb * P;
+    float2* Zb = Z + bb * P;
     if (k == 0) {
-      const float2 x = X[0];  // (DC, Nyquist)
-      Z[0] = make_float2(x.x + x.y, x.x - x.y);
+      const float2 x = Xb[0];  // (DC, Nyquist)
+      Zb[0] = make_float2(x.x + x.y, x.x - x.y);
       continue;
     }
-    const float2 xk = X[k], xm = cconj(X[P - k]);
+    const float2 xk = Xb[k], xm = cconj(Xb[P - k]);
     const float2 E = cadd(xk, xm);
     const float2 O = cmul(csub(xk, xm), cconj(tw2[k]));
     const float2 iO = make_float2(-O.y, O.x);
-    Z[k] = cadd(E, iO);
+    Zb[k] = cadd(E, iO);
     if (k != P - k) {
       const float2 iOc = make_float2(O.y, O.x);  // i * conj(O)
-      Z[P - k] = cadd(cconj(E), iOc);
+      Zb[P - k] = cadd(cconj(E), iOc);
     }
   }
   __syncthreads();

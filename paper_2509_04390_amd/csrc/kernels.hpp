@@ -2,24 +2,28 @@
 //
 // Two launches per audio block, ordered on one stream.
 //
-// k_mac: workgroup i runs work item i of the block's phase list.  Items of
-// kind MAC0 cover the uniform first tier (partition = block, Sec. IV): an
-// item owns a group of G outputs, one input q, a partition range [p0, p1) and
-// a slice of bins, and computes
-//     Y_l[k] += sum_{p in [p0,p1)} H_{l,q,p}[k] * X_q[(n - p) mod K][k]
-// (Sec. IV step 2, frequency-domain delay line as a ring with a head index).
-// Items whose range starts at p = 0 transform the current input window
-// themselves (Sec. IV step 1: last 2B samples, real FFT), so no launch is
-// spent on the forward transform; one of them stores that spectrum into the
-// ring slot n mod K for later blocks.  Each item writes its partial sums to
-// its own slot.
+// The frequency-domain delay line (Sec. IV step 2) gives every output block
+//     Y_l[k] = sum_q sum_{p<K} H_{l,q,p}[k] * X_q[(n - p) mod K][k].
+// Only the p = 0 term needs the block that has just arrived; the terms
+// p >= 1 use spectra already in the delay line.  So block n is produced by
 //
-// k_final: one workgroup per output group adds the group's slots in a fixed
-// order, runs the inverse real FFT and keeps the second half of the 2B
-// samples (overlap-save, Sec. IV step 3).
+// k_head (latency-critical, one workgroup per output group): real FFT of
+//   each input's window [x_{n-1}, x_n] (Sec. IV step 1, batched in LDS),
+//   store it into ring slot n mod K, add sum_q H_{l,q,0} * X_q, add the
+//   partial sums of the p >= 1 terms that k_tail computed beforehand, run the
+//   inverse real FFT and keep the second half of the 2B samples
+//   (overlap-save, Sec. IV step 3), then advance the device block index;
 //
-// The block index lives in device memory and k_final advances it, so
-// identical launches (and graph replays) process successive blocks.
+// k_tail (bandwidth-bound, launched right after the head of block n-1, so it
+//   runs while the host waits for the next audio block): work item i covers a
+//   group of G outputs, one input, a partition range [p0, p1) with p0 >= 1
+//   and a slice of bins, and writes
+//       sum_{p in [p0,p1)} H_{l,q,p}[k] * X_q[(n - p) mod K][k]
+//   to its own partial-sum slot.
+//
+// The sum is the same as forming all K terms at once; only when each term is
+// formed changes.  Every partial slot is written by exactly one item and read
+// in a fixed order, so results are reproducible bit for bit.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -33,12 +37,11 @@ constexpr int kThreads = 256;
 constexpr int kMaxTiers = 8;
 constexpr int kUnroll = 4;
 
-enum ItemKind : int32_t { K_MAC0 = 0, K_MAC = 1, K_FFT = 2, K_NOP = 3 };
-enum ItemFlag : int32_t { F_WRITE_X = 1, F_WRITE_HIST = 2, F_FINAL = 4 };
+enum ItemKind : int32_t { K_MAC = 0, K_NOP = 1 };
 
 struct Item {          // one workgroup's work in one block (48 bytes)
   int32_t kind;        // ItemKind
-  int32_t flags;       // ItemFlag bits
+  int32_t flags;
   int32_t tier;
   int32_t group;       // reduction group (outputs l0 .. l0+nl-1)
   int32_t q;           // input channel
@@ -86,6 +89,8 @@ struct KArgs {
   int64_t ring_mask;         // output ring length - 1
   int32_t B, Q, L, n_tiers;
   int32_t n_phase, max_items;
+  int32_t head_nq;           // inputs transformed per pass in k_head
+  int32_t pad;
 };
 
 // ---------------------------------------------------------------------------
@@ -106,6 +111,7 @@ template <> struct HVec<float2> {
     h[0] = make_float2(v.x, v.y);
     h[1] = make_float2(v.z, v.w);
   }
+  static __device__ __forceinline__ float2 load1(const float2* p) { return *p; }
 };
 
 template <> struct HVec<f16c_t> {
@@ -123,6 +129,12 @@ template <> struct HVec<f16c_t> {
       h[j] = make_float2((float)re, (float)im);
     }
   }
+  static __device__ __forceinline__ float2 load1(const f16c_t* p) {
+    const uint32_t w = p->bits;
+    const _Float16 re = __builtin_bit_cast(_Float16, (uint16_t)(w & 0xffffu));
+    const _Float16 im = __builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
+    return make_float2((float)re, (float)im);
+  }
 };
 
 template <> struct HVec<bf16c_t> {
@@ -132,6 +144,10 @@ template <> struct HVec<bf16c_t> {
 #pragma unroll
     for (int j = 0; j < 4; ++j)
       h[j] = make_float2(__uint_as_float(v[j] << 16), __uint_as_float(v[j] & 0xffff0000u));
+  }
+  static __device__ __forceinline__ float2 load1(const bf16c_t* p) {
+    const uint32_t w = p->bits;
+    return make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
   }
 };
 
@@ -152,13 +168,12 @@ __device__ __forceinline__ int wrap_slot(int64_t v, int K) {
 
 // ---------------------------------------------------------------------------
 // Multiply-accumulate of one item's partitions into its partial-sum slot.
-// x0 (LDS) holds the fresh spectrum of the current frame, used for p == 0.
-// `frame` is the frame whose delay-line head is slot frame mod K.
+// `frame` is the frame whose delay-line head is slot frame mod K (partition
+// p pairs with slot (frame - p) mod K).
 // ---------------------------------------------------------------------------
 template <typename HT, int G>
 __device__ void mac_item(const KArgs& A, const DevTier& T, const Item& it,
-                         const Group& grp, int64_t frame, const float2* x0,
-                         float2* red) {
+                         const Group& grp, int64_t frame, float2* red) {
   constexpr int C = HVec<HT>::C;
   const int P = T.P;
   const int W = P < kThreads * C ? P : kThreads * C;  // bins per item slice
@@ -192,35 +207,10 @@ __device__ void mac_item(const KArgs& A, const DevTier& T, const Item& it,
 #pragma unroll
     for (int j = 0; j < C; ++j) acc[g][j][0] = acc[g][j][1] = acc[g][j][2] = acc[g][j][3] = 0.f;
 
-  auto mac = [&](int g, const float2 (&h)[C], const float2 (&x)[C]) {
-#pragma unroll
-    for (int j = 0; j < C; ++j) {
-      acc[g][j][0] += h[j].x * x[j].x;   // Re H Re X
-      acc[g][j][1] += h[j].y * x[j].y;   // Im H Im X
-      acc[g][j][2] += h[j].x * x[j].y;   // Re H Im X
-      acc[g][j][3] += h[j].y * x[j].x;   // Im H Re X
-    }
-  };
-
-  int p = it.p0 + s;
-  if (x0 != nullptr && p == 0) {
-    float2 x[C];
-#pragma unroll
-    for (int j = 0; j < C; ++j) x[j] = x0[kb + j];
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      if (0 < pend[g]) {
-        float2 h[C];
-        HVec<HT>::load(hb[g], h);
-        mac(g, h, x);
-      }
-    }
-    p += RP;
-  }
-
   const int K = T.K;
   const float2* Xq = T.X + (int64_t)q * K * P + kb;
   const int step = RP % K;
+  int p = it.p0 + s;
   int slot = wrap_slot(frame - p, K);
   for (; p < it.p1; p += RP * kUnroll) {
     float2 xv[kUnroll][C];
@@ -251,7 +241,14 @@ __device__ void mac_item(const KArgs& A, const DevTier& T, const Item& it,
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u)
 #pragma unroll
-      for (int g = 0; g < G; ++g) mac(g, hv[u][g], xv[u]);
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+          acc[g][j][0] += hv[u][g][j].x * xv[u][j].x;   // Re H Re X
+          acc[g][j][1] += hv[u][g][j].y * xv[u][j].y;   // Im H Im X
+          acc[g][j][2] += hv[u][g][j].x * xv[u][j].y;   // Re H Im X
+          acc[g][j][3] += hv[u][g][j].y * xv[u][j].x;   // Im H Re X
+        }
   }
 
   // combine the four real sums; packed bin 0 holds two real products
@@ -274,7 +271,6 @@ __device__ void mac_item(const KArgs& A, const DevTier& T, const Item& it,
       for (int j = 0; j < C; ++j) part[(int64_t)g * P + kb + j] = res[g][j];
     return;
   }
-  __syncthreads();  // x0 may share LDS with `red`
 #pragma unroll
   for (int g = 0; g < G; ++g)
 #pragma unroll
@@ -288,125 +284,97 @@ __device__ void mac_item(const KArgs& A, const DevTier& T, const Item& it,
   }
 }
 
-// Real FFT of the window [x_{n-1}, x_n] of input q (2B samples, first tier).
-// Returns the LDS buffer holding the packed spectrum.
-__device__ float2* first_tier_spectrum(const KArgs& A, const DevTier& T, int q,
-                                       int64_t n, float2* a, float2* b) {
-  const int P = T.P;  // == B
-  const float* hq = A.hist + (int64_t)q * (A.hist_mask + 1);
-  const float* iq = A.in + (int64_t)q * A.B;
-  for (int m = threadIdx.x; m < P; m += kThreads) {
-    float w[2];
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const int i = 2 * m + e;
-      w[e] = i < P ? hq[((n - 1) * A.B + i) & A.hist_mask] : iq[i - P];
-    }
-    a[m] = make_float2(w[0], w[1]);
-  }
-  __syncthreads();
-  float2* z = fft_stockham<false>(a, b, P, T.logP, T.tw);
-  float2* x = (z == a) ? b : a;
-  rfft_post(z, x, P, T.tw + P);
-  return x;
+// Twiddle tables of tiers up to this size are staged in LDS before an FFT;
+// larger ones are read from global memory (they stay hot in L1/L2).
+constexpr int kTwLdsMaxP = 1024;
+__host__ __device__ constexpr int tw_lds_len(int P) { return P <= kTwLdsMaxP ? 2 * P : 0; }
+
+// Returns the twiddle table to use: a copy in LDS at `dst` when it fits,
+// otherwise the global table.  No barrier: the caller's next barrier
+// publishes the copy.
+__device__ __forceinline__ const float2* stage_twiddles(const DevTier& T, float2* dst) {
+  const int n = tw_lds_len(T.P);
+  if (n == 0) return T.tw;
+  for (int i = threadIdx.x; i < n; i += kThreads) dst[i] = T.tw[i];
+  return dst;
 }
 
 // Sum the group's partial slots for output g of the group into LDS `y`.
+// With P < 256 bins the 256 threads form 256/P groups that each add a
+// contiguous run of slots, then the runs are added in group order; the order
+// is fixed by (P, nslot), so results are reproducible.  `scratch` holds 256
+// float2.  Ends with a barrier.
 template <int G>
-__device__ void reduce_slots(const DevTier& T, const Group& grp, int g, float2* y) {
+__device__ void reduce_slots(const DevTier& T, const Group& grp, int g, float2* y,
+                             float2* scratch) {
   const int P = T.P;
-  const float2* base = T.partial + (int64_t)grp.slot0 * G * P + (int64_t)g * P;
-  for (int k = threadIdx.x; k < P; k += kThreads) {
-    float2 acc = make_float2(0.f, 0.f);
-#pragma unroll 8
-    for (int sl = 0; sl < grp.nslot; ++sl) acc = cadd(acc, base[(int64_t)sl * G * P + k]);
-    y[k] = acc;
+  const int64_t stride = (int64_t)G * P;
+  const float2* base = T.partial + (int64_t)grp.slot0 * stride + (int64_t)g * P;
+  const int tid = threadIdx.x;
+  if (P >= kThreads) {
+    for (int k = tid; k < P; k += kThreads) {
+      float2 acc = make_float2(0.f, 0.f);
+#pragma unroll 16
+      for (int sl = 0; sl < grp.nslot; ++sl) acc = cadd(acc, base[sl * stride + k]);
+      y[k] = acc;
+    }
+    __syncthreads();
+    return;
+  }
+  const int ng = kThreads / P;
+  const int k = tid % P, tg = tid / P;
+  const int per = (grp.nslot + ng - 1) / ng;
+  const int s0 = min(grp.nslot, tg * per), s1 = min(grp.nslot, s0 + per);
+  float2 acc = make_float2(0.f, 0.f);
+#pragma unroll 16
+  for (int sl = s0; sl < s1; ++sl) acc = cadd(acc, base[sl * stride + k]);
+  scratch[tid] = acc;
+  __syncthreads();
+  if (tid < P) {
+    float2 t = scratch[k];
+    for (int g2 = 1; g2 < ng; ++g2) t = cadd(t, scratch[g2 * P + k]);
+    y[k] = t;
   }
   __syncthreads();
 }
 
-// Last workgroup of a first-tier group: reduce, inverse real FFT, keep the
-// last B samples, add the later tiers' contributions from their output rings
-// and emit the block.
-template <int G>
-__device__ void first_tier_final(const KArgs& A, const DevTier& T, const Group& grp,
-                                 int64_t n, float2* a, float2* b) {
-  const int P = T.P;  // == B
-  const float scale = 1.0f / (float)(2 * P);
-  for (int g = 0; g < grp.nl; ++g) {
-    const int l = grp.l0 + g;
-    reduce_slots<G>(T, grp, g, a);
-    irfft_pre(a, b, P, T.tw + P);
-    float2* z = fft_stockham<true>(b, a, P, T.logP, T.tw);
-    float* o = A.out + (int64_t)l * A.B;
-    for (int m = (P >> 1) + threadIdx.x; m < P; m += kThreads) {
-      const float2 v = z[m];
-      const int i = 2 * (m - (P >> 1));
-      float y0 = v.x * scale, y1 = v.y * scale;
-      for (int t = 1; t < A.n_tiers; ++t) {
-        float* ring = A.tier[t].oring + (int64_t)l * (A.ring_mask + 1);
-        const int64_t s0 = (n * A.B + i) & A.ring_mask;
-        const int64_t s1 = (n * A.B + i + 1) & A.ring_mask;
-        y0 += ring[s0];
-        y1 += ring[s1];
-        ring[s0] = 0.f;
-        ring[s1] = 0.f;
-      }
-      o[i] = y0;
-      o[i + 1] = y1;
-    }
-    __syncthreads();
-  }
+// LDS layout of k_head, in float2 units (the host sizes the launch with the
+// same function): Y [G][P] | Xa [nbuf][P] | Xb [nbuf][P] | twiddles | 256.
+struct HeadLds {
+  int y, xa, xb, tw, scratch, total;
+};
+__host__ __device__ inline HeadLds head_lds(int P, int G, int nq) {
+  const int nbuf = nq > G ? nq : G;
+  HeadLds h;
+  h.y = 0;
+  h.xa = G * P;
+  h.xb = h.xa + nbuf * P;
+  h.tw = h.xb + nbuf * P;
+  h.scratch = h.tw + tw_lds_len(P);
+  h.total = h.scratch + kThreads;
+  return h;
 }
 
 template <typename HT, int G>
-__global__ __launch_bounds__(kThreads) void k_mac(const KArgs A) {
+__global__ __launch_bounds__(kThreads) void k_tail(const KArgs A) {
   extern __shared__ float2 lds[];
-  const int tid = threadIdx.x;
-  const int64_t n = A.state->block;  // advanced only by k_final of the previous block
-  const int phase = (int)(n % A.n_phase);
+  const int64_t frame = A.state->block;  // the block whose head comes next
+  const int phase = (int)(frame % A.n_phase);
   if ((int)blockIdx.x >= A.phase_count[phase]) return;
   const Item it = A.items[(int64_t)phase * A.max_items + blockIdx.x];
   if (it.kind == K_NOP) return;
-
-  const DevTier& T = A.tier[it.tier];
-  const Group grp = A.groups[it.group];
-  float2* bufA = lds;
-  float2* bufB = lds + T.P;
-
-  if (it.kind == K_MAC0) {
-    const float2* x0 = nullptr;
-    if (it.p0 == 0) {
-      float2* xs = first_tier_spectrum(A, T, it.q, n, bufA, bufB);
-      constexpr int C = HVec<HT>::C;
-      const int W = T.P < kThreads * C ? T.P : kThreads * C;
-      if (it.flags & F_WRITE_X) {
-        float2* dst = T.X + ((int64_t)it.q * T.K + wrap_slot(n, T.K)) * T.P;
-        for (int k = it.k0 + tid; k < it.k0 + W; k += kThreads) dst[k] = xs[k];
-      }
-      if (it.flags & F_WRITE_HIST) {
-        float* hq = A.hist + (int64_t)it.q * (A.hist_mask + 1);
-        const float* iq = A.in + (int64_t)it.q * A.B;
-        for (int i = tid; i < A.B; i += kThreads) hq[(n * A.B + i) & A.hist_mask] = iq[i];
-      }
-      x0 = xs;
-    }
-    mac_item<HT, G>(A, T, it, grp, n, x0, lds);
-  }
+  mac_item<HT, G>(A, A.tier[it.tier], it, A.groups[it.group], frame, lds);
 }
 
-// One workgroup per output group: reduce the group's partial slots, inverse
-// FFT, overlap-save output.  Runs after k_mac of the same block on the same
-// stream, so every partial is visible without in-kernel fences.  The last
-// workgroup to read the block index advances it for the next block.
-template <int G>
-__global__ __launch_bounds__(kThreads) void k_final(const KArgs A) {
+template <typename HT, int G>
+__global__ __launch_bounds__(kThreads) void k_head(const KArgs A) {
   extern __shared__ float2 lds[];
   __shared__ int64_t sh_n;
-  if (threadIdx.x == 0) sh_n = A.state->block;
+  const int tid = threadIdx.x;
+  if (tid == 0) sh_n = A.state->block;
   __syncthreads();
   const int64_t n = sh_n;
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
     const uint32_t old = __hip_atomic_fetch_add(&A.state->arrive, 1u, __ATOMIC_RELAXED,
                                                 __HIP_MEMORY_SCOPE_AGENT);
     if (old == gridDim.x - 1) {  // every workgroup has read n
@@ -416,7 +384,123 @@ __global__ __launch_bounds__(kThreads) void k_final(const KArgs A) {
   }
   const DevTier& T = A.tier[0];
   const Group grp = A.groups[blockIdx.x];
-  first_tier_final<G>(A, T, grp, n, lds, lds + T.P);
+  const int P = T.P, logP = T.logP;  // P == B
+  const HeadLds L = head_lds(P, G, A.head_nq);
+  float2* Y = lds + L.y;
+  float2* Xa = lds + L.xa;
+  float2* Xb = lds + L.xb;
+  float2* scratch = lds + L.scratch;
+  const float2* tw = stage_twiddles(T, lds + L.tw);
+  const HT* Hbase = reinterpret_cast<const HT*>(T.H);
+
+  // 1. the p >= 1 terms, summed by k_tail before this launch
+  for (int g = 0; g < grp.nl; ++g) reduce_slots<G>(T, grp, g, Y + g * P, scratch);
+
+  // 2. the p = 0 term: window -> real FFT -> ring slot n mod K, times H_{l,q,0}
+  const int slot = wrap_slot(n, T.K);
+  for (int q0 = 0; q0 < A.Q; q0 += A.head_nq) {
+    const int nb = min(A.head_nq, A.Q - q0);
+    for (int e = tid; e < nb * P; e += kThreads) {
+      const int b = e / P, m = e - b * P;
+      const int q = q0 + b;
+      const float* hq = A.hist + (int64_t)q * (A.hist_mask + 1);
+      const float* iq = A.in + (int64_t)q * A.B;
+      const int i0 = 2 * m, i1 = 2 * m + 1;
+      const float w0 = i0 < P ? hq[((n - 1) * A.B + i0) & A.hist_mask] : iq[i0 - P];
+      const float w1 = i1 < P ? hq[((n - 1) * A.B + i1) & A.hist_mask] : iq[i1 - P];
+      Xa[e] = make_float2(w0, w1);
+    }
+    __syncthreads();
+    float2* z = fft_stockham<false>(Xa, Xb, P, logP, tw, nb);
+    float2* x = (z == Xa) ? Xb : Xa;
+    rfft_post(z, x, P, tw + P, nb);
+    if (blockIdx.x == 0) {
+      for (int e = tid; e < nb * P; e += kThreads) {
+        const int b = e / P, k = e - b * P;
+        T.X[((int64_t)(q0 + b) * T.K + slot) * P + k] = x[e];
+      }
+      for (int e = tid; e < nb * A.B; e += kThreads) {
+        const int b = e / A.B, i = e - b * A.B;
+        const int q = q0 + b;
+        A.hist[(int64_t)q * (A.hist_mask + 1) + ((n * A.B + i) & A.hist_mask)] =
+            A.in[(int64_t)q * A.B + i];
+      }
+    }
+    for (int e = tid; e < grp.nl * P; e += kThreads) {
+      const int g = e / P, k = e - g * P;
+      const int l = grp.l0 + g;
+      float2 acc = Y[e];
+      for (int b = 0; b < nb; ++b) {
+        const int pair = l * A.Q + q0 + b;
+        const int64_t row = T.pair_row[pair];
+        if (row < 0) continue;
+        const float2 h = HVec<HT>::load1(Hbase + row * (int64_t)P + k);
+        const float2 xv = x[b * P + k];
+        if (k == 0)
+          acc = make_float2(acc.x + h.x * xv.x, acc.y + h.y * xv.y);
+        else
+          acc = cadd(acc, cmul(h, xv));
+      }
+      Y[e] = acc;
+    }
+    __syncthreads();
+  }
+
+  // 3. inverse real FFT of the group's outputs, keep the last B samples, add
+  //    the later tiers' contributions from their output rings, emit
+  irfft_pre(Y, Xa, P, tw + P, grp.nl);
+  float2* z = fft_stockham<true>(Xa, Xb, P, logP, tw, grp.nl);
+  const float scale = 1.0f / (float)(2 * P);
+  const int half = P >> 1;
+  for (int e = tid; e < grp.nl * half; e += kThreads) {
+    const int g = e / half, m = half + (e - g * half);
+    const int l = grp.l0 + g;
+    const float2 v = z[g * P + m];
+    const int i = 2 * (m - half);
+    float y0 = v.x * scale, y1 = v.y * scale;
+    for (int t = 1; t < A.n_tiers; ++t) {
+      float* ring = A.tier[t].oring + (int64_t)l * (A.ring_mask + 1);
+      const int64_t s0 = (n * A.B + i) & A.ring_mask;
+      const int64_t s1 = (n * A.B + i + 1) & A.ring_mask;
+      y0 += ring[s0];
+      y1 += ring[s1];
+      ring[s0] = 0.f;
+      ring[s1] = 0.f;
+    }
+    A.out[(int64_t)l * A.B + i] = y0;
+    A.out[(int64_t)l * A.B + i + 1] = y1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Streaming-read probe (measurement aid): workgroup w reads its contiguous
+// chunk of n16 16-byte vectors with the same non-temporal loads as k_mac,
+// kUnroll vectors in flight per thread, and writes one float so the loads
+// are not removed.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_read_probe(const f32x4* __restrict__ buf,
+                                                        int64_t n16, float* sink) {
+  __shared__ float red[kThreads];
+  const int64_t per = (n16 + gridDim.x - 1) / gridDim.x;
+  const int64_t b0 = (int64_t)blockIdx.x * per;
+  const int64_t b1 = min(n16, b0 + per);
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  int64_t i = b0 + threadIdx.x;
+  for (; i + (kUnroll - 1) * kThreads < b1; i += kUnroll * kThreads) {
+    f32x4 v[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) v[u] = __builtin_nontemporal_load(buf + i + u * kThreads);
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) acc += v[u];
+  }
+  for (; i < b1; i += kThreads) acc += __builtin_nontemporal_load(buf + i);
+  red[threadIdx.x] = acc.x + acc.y + acc.z + acc.w;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = 0.f;
+    for (int k = 0; k < kThreads; ++k) t += red[k];
+    sink[blockIdx.x] = t;
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -74,8 +74,10 @@ struct rta_ctx {
   TierHost tier[kMaxTiers];
   int G = 1, rows_per_item = 0, grid = 0, n_phase = 1, max_items = 0;
   int64_t hist_len = 0, ring_len = 0;
-  size_t lds_bytes = 0;        // k_mac dynamic LDS
-  size_t lds_final_bytes = 0;  // k_final dynamic LDS
+  size_t lds_tail = 0;         // k_tail dynamic LDS
+  size_t lds_head = 0;         // k_head dynamic LDS
+  int head_nq = 1;             // inputs transformed per pass in k_head
+  hipEvent_t done = nullptr;   // recorded after an rta_process output copy
 
   float* hist = nullptr;
   Item* items = nullptr;
@@ -84,10 +86,10 @@ struct rta_ctx {
   DevState* state = nullptr;
   int n_groups = 0;
 
-  float* d_in = nullptr;
-  float* d_out = nullptr;
-  float* h_in = nullptr;
+  float* h_in = nullptr;    // pinned host staging, mapped into the device
   float* h_out = nullptr;
+  float* m_in = nullptr;    // device addresses of h_in / h_out
+  float* m_out = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
 
@@ -96,7 +98,7 @@ struct rta_ctx {
   std::vector<hipEvent_t> events;  // 3 per timed block
   size_t events_used = 0;
   int64_t device_bytes = 0, spectra_bytes = 0;
-  double h_bytes = 0, x_bytes = 0, io_bytes = 0, cmacs = 0;
+  double h_bytes = 0, x_bytes = 0, io_bytes = 0, cmacs = 0, tail_bytes = 0;
   std::vector<void*> dev_allocs;
 };
 
@@ -149,29 +151,23 @@ std::vector<float2> twiddles(int P) {
 
 using BlockKernel = void (*)(const KArgs);
 
-BlockKernel mac_kernel(int dtype, int G) {
-#define RTA_PICK(HT)                                   \
+#define RTA_PICK(KERNEL, HT)                           \
   switch (G) {                                         \
-    case 1: return k_mac<HT, 1>;                       \
-    case 2: return k_mac<HT, 2>;                       \
-    case 4: return k_mac<HT, 4>;                       \
+    case 1: return KERNEL<HT, 1>;                      \
+    case 2: return KERNEL<HT, 2>;                      \
+    case 4: return KERNEL<HT, 4>;                      \
     default: return nullptr;                           \
   }
-  if (dtype == RTA_FP32) RTA_PICK(float2)
-  if (dtype == RTA_FP16) RTA_PICK(f16c_t)
-  if (dtype == RTA_BF16) RTA_PICK(bf16c_t)
-#undef RTA_PICK
+#define RTA_DISPATCH(KERNEL)                           \
+  if (dtype == RTA_FP32) RTA_PICK(KERNEL, float2)      \
+  if (dtype == RTA_FP16) RTA_PICK(KERNEL, f16c_t)      \
+  if (dtype == RTA_BF16) RTA_PICK(KERNEL, bf16c_t)     \
   return nullptr;
-}
 
-BlockKernel final_kernel(int G) {
-  switch (G) {
-    case 1: return k_final<1>;
-    case 2: return k_final<2>;
-    case 4: return k_final<4>;
-    default: return nullptr;
-  }
-}
+BlockKernel tail_kernel(int dtype, int G) { RTA_DISPATCH(k_tail) }
+BlockKernel head_kernel(int dtype, int G) { RTA_DISPATCH(k_head) }
+#undef RTA_DISPATCH
+#undef RTA_PICK
 
 int vec_bins(int dtype) { return dtype == RTA_FP32 ? 2 : 4; }
 
@@ -237,7 +233,9 @@ int validate(double fs, int32_t block, const rta_scheme* scheme, int32_t n_in, i
 }
 
 // ---------------------------------------------------------------------------
-// Work lists for the uniform first tier.
+// Work lists of k_tail for the uniform first tier: partitions p >= 1 of every
+// (output group, input) are cut into chunks of about R rows, each chunk into
+// bin slices; each chunk owns one partial-sum slot of its group.
 // ---------------------------------------------------------------------------
 struct Bucket {
   int q, p0, k0;
@@ -253,15 +251,16 @@ int build_plan(rta_ctx* c, std::vector<Item>& flat, std::vector<Group>& groups) 
   const int nslice = P / W;
   const int G = c->G;
   const int ngroups = (c->L + G - 1) / G;
+  auto group_rows = [&](int l0, int nl, int q) {
+    int kg = 0;
+    for (int l = l0; l < l0 + nl; ++l) kg = std::max(kg, T.kp[l * c->Q + q]);
+    return kg;
+  };
 
-  // total partition rows of the groups, to size the items
   int64_t total_rows = 0;
   for (int g = 0; g < ngroups; ++g)
-    for (int q = 0; q < c->Q; ++q) {
-      int kg = 0;
-      for (int l = g * G; l < std::min(c->L, g * G + G); ++l) kg = std::max(kg, T.kp[l * c->Q + q]);
-      total_rows += kg;
-    }
+    for (int q = 0; q < c->Q; ++q)
+      total_rows += std::max(0, group_rows(g * G, std::min(G, c->L - g * G), q) - 1);
   int R = c->rows_per_item;
   if (R <= 0) {
     const int64_t target_items = env_int("RTA_TARGET_ITEMS", 2048);
@@ -270,7 +269,6 @@ int build_plan(rta_ctx* c, std::vector<Item>& flat, std::vector<Group>& groups) 
   c->rows_per_item = R;
 
   std::vector<Bucket> buckets;
-  std::vector<int> writer_done(c->Q, 0);
   groups.clear();
   int slot = 0;
   for (int g = 0; g < ngroups; ++g) {
@@ -279,17 +277,17 @@ int build_plan(rta_ctx* c, std::vector<Item>& flat, std::vector<Group>& groups) 
     gr.nl = std::min(G, c->L - gr.l0);
     gr.slot0 = slot;
     gr.nslot = 0;
-    std::vector<std::pair<int, Item>> mine;  // bucket key index, item
     for (int q = 0; q < c->Q; ++q) {
-      int kg = 0;
-      for (int l = gr.l0; l < gr.l0 + gr.nl; ++l) kg = std::max(kg, T.kp[l * c->Q + q]);
-      if (kg == 0) continue;
-      const int nch = (kg + R - 1) / R;
+      const int kg = group_rows(gr.l0, gr.nl, q);
+      if (kg <= 1) continue;  // partition 0 is done by k_head
+      const int rows = kg - 1;
+      const int nch = (rows + R - 1) / R;
       for (int ch = 0; ch < nch; ++ch) {
-        const int p0 = (int)((int64_t)ch * kg / nch), p1 = (int)((int64_t)(ch + 1) * kg / nch);
+        const int p0 = 1 + (int)((int64_t)ch * rows / nch);
+        const int p1 = 1 + (int)((int64_t)(ch + 1) * rows / nch);
         for (int sl = 0; sl < nslice; ++sl) {
           Item it{};
-          it.kind = K_MAC0;
+          it.kind = K_MAC;
           it.tier = 0;
           it.group = g;
           it.q = q;
@@ -297,49 +295,28 @@ int build_plan(rta_ctx* c, std::vector<Item>& flat, std::vector<Group>& groups) 
           it.p1 = p1;
           it.k0 = sl * W;
           it.slot = slot;
-          if (p0 == 0 && !writer_done[q]) {
-            it.flags |= F_WRITE_X;
-            if (sl == 0) it.flags |= F_WRITE_HIST;
+          auto bit = std::find_if(buckets.begin(), buckets.end(), [&](const Bucket& b) {
+            return b.q == q && b.p0 == p0 && b.k0 == it.k0;
+          });
+          if (bit == buckets.end()) {
+            buckets.push_back(Bucket{q, p0, it.k0, {}, 0});
+            bit = buckets.end() - 1;
           }
-          mine.push_back({0, it});
+          bit->items.push_back(it);
+          bit->rows += (int64_t)(p1 - p0) * gr.nl;
         }
         ++slot;
         ++gr.nslot;
       }
-      writer_done[q] = 1;
-    }
-    if (gr.nslot == 0) {  // an output with no path still emits every block
-      Item it{};
-      it.kind = K_MAC0;
-      it.group = g;
-      it.q = 0;
-      it.p0 = it.p1 = 0;
-      it.k0 = 0;
-      it.slot = slot++;
-      gr.nslot = 1;
-      mine.push_back({0, it});
-    }
-    for (auto& m : mine) m.second.target = (int)mine.size();
-    // bucket by (q, p0, k0): items that read the same delay-line rows
-    for (auto& m : mine) {
-      const Item& it = m.second;
-      auto bit = std::find_if(buckets.begin(), buckets.end(), [&](const Bucket& b) {
-        return b.q == it.q && b.p0 == it.p0 && b.k0 == it.k0;
-      });
-      if (bit == buckets.end()) {
-        buckets.push_back(Bucket{it.q, it.p0, it.k0, {}, 0});
-        bit = buckets.end() - 1;
-      }
-      bit->items.push_back(it);
-      bit->rows += (int64_t)(it.p1 - it.p0) * gr.nl;
     }
     groups.push_back(gr);
   }
   T.nslots = slot;
   c->n_groups = (int)groups.size();
 
-  // XCD-aware placement: a bucket's items all get list positions with the
-  // same residue mod 8, so its delay-line rows are fetched into one L2.
+  // XCD-aware placement: a bucket's items (same input, partitions and bins,
+  // different outputs) all get list positions with the same residue mod 8, so
+  // they run on one XCD and its delay-line rows are fetched into one L2.
   std::vector<std::vector<Item>> xl(kXcds);
   std::vector<int64_t> load(kXcds, 0);
   std::stable_sort(buckets.begin(), buckets.end(),
@@ -355,22 +332,23 @@ int build_plan(rta_ctx* c, std::vector<Item>& flat, std::vector<Group>& groups) 
   for (auto& it : flat) it.kind = K_NOP;
   for (int x = 0; x < kXcds; ++x)
     for (size_t i = 0; i < xl[x].size(); ++i) flat[i * kXcds + x] = xl[x][i];
-  // trim trailing no-ops
   while (!flat.empty() && flat.back().kind == K_NOP) flat.pop_back();
 
-  // every index the block kernel derives from an item must stay inside the
+  // every index the kernels derive from an item must stay inside the
   // buffers allocated for this plan
+  for (const Group& gr : groups)
+    if (gr.l0 < 0 || gr.nl < 1 || gr.nl > G || gr.l0 + gr.nl > c->L || gr.slot0 < 0 ||
+        gr.nslot < 0 || gr.slot0 + gr.nslot > T.nslots)
+      return RTA_E_STATE;
   for (const Item& it : flat) {
     if (it.kind == K_NOP) continue;
-    if (it.kind != K_MAC0 || it.tier != 0) return RTA_E_STATE;
+    if (it.kind != K_MAC || it.tier != 0) return RTA_E_STATE;
     if (it.group < 0 || it.group >= (int)groups.size()) return RTA_E_STATE;
     const Group& gr = groups[it.group];
     if (it.q < 0 || it.q >= c->Q) return RTA_E_STATE;
-    if (it.p0 < 0 || it.p1 < it.p0 || it.p1 > T.K) return RTA_E_STATE;
+    if (it.p0 < 1 || it.p1 < it.p0 || it.p1 > T.K) return RTA_E_STATE;
     if (it.k0 < 0 || it.k0 % W != 0 || it.k0 + W > P) return RTA_E_STATE;
-    if (it.slot < gr.slot0 || it.slot >= gr.slot0 + gr.nslot || it.slot >= T.nslots) return RTA_E_STATE;
-    if (it.target < 1) return RTA_E_STATE;
-    if (gr.l0 < 0 || gr.nl < 1 || gr.nl > G || gr.l0 + gr.nl > c->L) return RTA_E_STATE;
+    if (it.slot < gr.slot0 || it.slot >= gr.slot0 + gr.nslot) return RTA_E_STATE;
   }
   return RTA_OK;
 }
@@ -407,14 +385,22 @@ KArgs make_args(const rta_ctx* c, const float* in, float* out) {
   a.n_tiers = c->n_tiers;
   a.n_phase = c->n_phase;
   a.max_items = c->max_items;
+  a.head_nq = c->head_nq;
   return a;
 }
 
-// The two launches of one block, in stream order.
+// The head of this block (output) and the tail of the next one.
+void enqueue_head(const rta_ctx* c, const KArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(head_kernel(c->dtype, c->G), dim3(c->n_groups), dim3(kThreads), c->lds_head, s, a);
+}
+void enqueue_tail(const rta_ctx* c, const KArgs& a, hipStream_t s) {
+  if (c->grid > 0)
+    hipLaunchKernelGGL(tail_kernel(c->dtype, c->G), dim3(c->grid), dim3(kThreads), c->lds_tail, s, a);
+}
 void enqueue_block(const rta_ctx* c, const float* in, float* out, hipStream_t s) {
   const KArgs a = make_args(c, in, out);
-  hipLaunchKernelGGL(mac_kernel(c->dtype, c->G), dim3(c->grid), dim3(kThreads), c->lds_bytes, s, a);
-  hipLaunchKernelGGL(final_kernel(c->G), dim3(c->n_groups), dim3(kThreads), c->lds_final_bytes, s, a);
+  enqueue_head(c, a, s);
+  enqueue_tail(c, a, s);
 }
 
 constexpr size_t kMaxTimedBlocks = 65536;
@@ -430,9 +416,9 @@ int launch_block(rta_ctx* c, const float* in, float* out, hipStream_t s) {
     c->events_used += 3;
     const KArgs a = make_args(c, in, out);
     HIP_TRY(c, hipEventRecord(e[0], s));
-    hipLaunchKernelGGL(mac_kernel(c->dtype, c->G), dim3(c->grid), dim3(kThreads), c->lds_bytes, s, a);
+    enqueue_head(c, a, s);
     HIP_TRY(c, hipEventRecord(e[1], s));
-    hipLaunchKernelGGL(final_kernel(c->G), dim3(c->n_groups), dim3(kThreads), c->lds_final_bytes, s, a);
+    enqueue_tail(c, a, s);
     HIP_TRY(c, hipEventRecord(e[2], s));
   } else {
     enqueue_block(c, in, out, s);
@@ -449,6 +435,11 @@ int zero_state(rta_ctx* c) {
       HIP_TRY(c, hipMemsetAsync(T.oring, 0, sizeof(float) * (size_t)c->L * c->ring_len, c->stream));
   }
   HIP_TRY(c, hipMemsetAsync(c->hist, 0, sizeof(float) * (size_t)c->Q * c->hist_len, c->stream));
+  // before the first head the p >= 1 terms are all zero (zero history)
+  for (int t = 0; t < c->n_tiers; ++t)
+    HIP_TRY(c, hipMemsetAsync(c->tier[t].partial, 0,
+                              sizeof(float2) * (size_t)std::max(1, c->tier[t].nslots) * c->G * c->tier[t].P,
+                              c->stream));
   HIP_TRY(c, hipMemsetAsync(c->state, 0, sizeof(DevState), c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return RTA_OK;
@@ -572,6 +563,11 @@ int create_impl(rta_ctx* c, const std::vector<int>& size, const std::vector<int>
     c->h_bytes += (double)rows * T.P * eb;
     c->cmacs += (double)rows * T.P;
     c->x_bytes += (double)c->Q * kmax * T.P * 8.0;
+    if (t == 0) {
+      double tail_rows = 0;
+      for (int32_t kp : T.kp) tail_rows += std::max(0, kp - 1);
+      c->tail_bytes = tail_rows * T.P * eb + (double)c->Q * std::max(0, kmax - 1) * T.P * 8.0;
+    }
     if ((st = dev_alloc(c, reinterpret_cast<char**>(&T.H), (size_t)std::max<int64_t>(1, rows) * T.P * eb)) != RTA_OK)
       return st;
     if ((st = dev_alloc(c, &T.pair_row, T.row.size())) != RTA_OK) return st;
@@ -590,6 +586,12 @@ int create_impl(rta_ctx* c, const std::vector<int>& size, const std::vector<int>
 
   // spectra
   if ((st = build_spectra(c, filters, lengths)) != RTA_OK) return st;
+
+  // outputs per group: as requested, halved until k_head's LDS fits
+  int max_lds = 0;
+  HIP_TRY(c, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
+  while (c->G > 1 && (int64_t)sizeof(float2) * head_lds(c->tier[0].P, c->G, 1).total + 64 > max_lds)
+    c->G /= 2;
 
   // work lists
   std::vector<Item> flat;
@@ -613,31 +615,35 @@ int create_impl(rta_ctx* c, const std::vector<int>& size, const std::vector<int>
     if ((st = dev_alloc(c, &T.partial, (size_t)std::max(1, T.nslots) * c->G * T.P)) != RTA_OK) return st;
   }
   if ((st = dev_alloc(c, &c->hist, (size_t)c->Q * c->hist_len)) != RTA_OK) return st;
-  if ((st = dev_alloc(c, &c->d_in, (size_t)c->Q * c->B)) != RTA_OK) return st;
-  if ((st = dev_alloc(c, &c->d_out, (size_t)c->L * c->B)) != RTA_OK) return st;
-  if (hipHostMalloc(reinterpret_cast<void**>(&c->h_in), sizeof(float) * (size_t)c->Q * c->B, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void**>(&c->h_out), sizeof(float) * (size_t)c->L * c->B, hipHostMallocDefault) != hipSuccess) {
+  // rta_process I/O: pinned host buffers that the kernels read and write
+  // directly over PCIe (no DMA copies on the latency path)
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->h_in), sizeof(float) * (size_t)c->Q * c->B,
+                    hipHostMallocMapped) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&c->h_out), sizeof(float) * (size_t)c->L * c->B,
+                    hipHostMallocMapped) != hipSuccess) {
     (void)hipGetLastError();
     return RTA_E_NOMEM;
   }
+  HIP_TRY(c, hipHostGetDevicePointer(reinterpret_cast<void**>(&c->m_in), c->h_in, 0));
+  HIP_TRY(c, hipHostGetDevicePointer(reinterpret_cast<void**>(&c->m_out), c->h_out, 0));
 
+  // LDS (kernels.hpp): k_tail needs the row-group reduction area; k_head
+  // holds the group's output spectra, two FFT buffers for head_nq inputs and
+  // the staged twiddles (HeadLds).  head_nq: as many inputs per pass as fit in
+  // 48 KB, at least one.
   const int C = vec_bins(c->dtype);
-  size_t lds = 0;
-  for (int t = 0; t < c->n_tiers; ++t) lds = std::max(lds, sizeof(float2) * 2 * (size_t)c->tier[t].P);
-  lds = std::max(lds, sizeof(float2) * (size_t)kThreads * C * c->G);
-  c->lds_bytes = lds;
-  c->lds_final_bytes = sizeof(float2) * 2 * (size_t)c->tier[0].P;
-  int max_lds = 0;
-  HIP_TRY(c, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
-  if ((int64_t)std::max(c->lds_bytes, c->lds_final_bytes) + 64 > (int64_t)max_lds)
-    return RTA_E_UNSUPPORTED;
-  if (c->lds_bytes > 65536)
-    HIP_TRY(c, hipFuncSetAttribute(reinterpret_cast<const void*>(mac_kernel(c->dtype, c->G)),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_bytes));
-  if (c->lds_final_bytes > 65536)
-    HIP_TRY(c, hipFuncSetAttribute(reinterpret_cast<const void*>(final_kernel(c->G)),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)c->lds_final_bytes));
+  c->lds_tail = sizeof(float2) * (size_t)kThreads * C * c->G;
+  const int P0 = c->tier[0].P;
+  const int fixed = head_lds(P0, c->G, 1).total - 2 * std::max(1, c->G) * P0;
+  c->head_nq = std::max(1, std::min(c->Q, (6144 - fixed) / (2 * P0)));
+  c->lds_head = sizeof(float2) * (size_t)head_lds(P0, c->G, c->head_nq).total;
+  if ((int64_t)std::max(c->lds_tail, c->lds_head) + 64 > (int64_t)max_lds) return RTA_E_UNSUPPORTED;
+  if (c->lds_tail > 65536)
+    HIP_TRY(c, hipFuncSetAttribute(reinterpret_cast<const void*>(tail_kernel(c->dtype, c->G)),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_tail));
+  if (c->lds_head > 65536)
+    HIP_TRY(c, hipFuncSetAttribute(reinterpret_cast<const void*>(head_kernel(c->dtype, c->G)),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_head));
 
   return zero_state(c);
 }
@@ -645,6 +651,7 @@ int create_impl(rta_ctx* c, const std::vector<int>& size, const std::vector<int>
 void free_all(rta_ctx* c) {
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
   c->events.clear();
+  if (c->done) (void)hipEventDestroy(c->done);
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
@@ -655,13 +662,12 @@ void free_all(rta_ctx* c) {
   if (c->stream) (void)hipStreamDestroy(c->stream);
 }
 
+// rta_process's block: the head kernel reading the pinned input and writing
+// the pinned output, captured once as a graph.
 int capture_graph(rta_ctx* c) {
+  const KArgs a = make_args(c, c->m_in, c->m_out);
   HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-  (void)hipMemcpyAsync(c->d_in, c->h_in, sizeof(float) * (size_t)c->Q * c->B,
-                       hipMemcpyHostToDevice, c->stream);
-  enqueue_block(c, c->d_in, c->d_out, c->stream);
-  (void)hipMemcpyAsync(c->h_out, c->d_out, sizeof(float) * (size_t)c->L * c->B,
-                       hipMemcpyDeviceToHost, c->stream);
+  enqueue_head(c, a, c->stream);
   HIP_TRY(c, hipStreamEndCapture(c->stream, &c->graph));
   HIP_TRY(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
   return RTA_OK;
@@ -691,6 +697,8 @@ int rta_create(rta_ctx** out, double fs, int32_t block, const rta_scheme* scheme
   if (c->G != 1 && c->G != 2 && c->G != 4) c->G = 1;
   c->rows_per_item = env_int("RTA_ROWS", 0);
   st = create_impl(c, size, count, filters, lengths);
+  if (st == RTA_OK && hipEventCreateWithFlags(&c->done, hipEventDisableTiming) != hipSuccess)
+    st = RTA_E_DEVICE;
   if (st == RTA_OK && !(flags & RTA_FLAG_NO_GRAPH)) st = capture_graph(c);
   if (st != RTA_OK) {
     free_all(c);
@@ -705,18 +713,23 @@ int rta_process(rta_ctx* c, const float* in, float* out) {
   if (c == nullptr || in == nullptr || out == nullptr) return RTA_E_ARG;
   if (c->poisoned) return RTA_E_DEVICE;
   std::memcpy(c->h_in, in, sizeof(float) * (size_t)c->Q * c->B);
+  const KArgs a = make_args(c, c->m_in, c->m_out);
   if (c->flags & RTA_FLAG_NO_GRAPH) {
-    HIP_TRY(c, hipMemcpyAsync(c->d_in, c->h_in, sizeof(float) * (size_t)c->Q * c->B,
-                              hipMemcpyHostToDevice, c->stream));
-    int st = launch_block(c, c->d_in, c->d_out, c->stream);
-    if (st != RTA_OK) return st;
-    HIP_TRY(c, hipMemcpyAsync(c->h_out, c->d_out, sizeof(float) * (size_t)c->L * c->B,
-                              hipMemcpyDeviceToHost, c->stream));
+    enqueue_head(c, a, c->stream);
+    HIP_TRY(c, hipGetLastError());
   } else {
     if (c->gexec == nullptr) return RTA_E_STATE;
     HIP_TRY(c, hipGraphLaunch(c->gexec, c->stream));
   }
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  // the output is complete when the head has finished; the next block's
+  // tail is enqueued behind it and is not waited for
+  HIP_TRY(c, hipEventRecord(c->done, c->stream));
+  enqueue_tail(c, a, c->stream);
+  HIP_TRY(c, hipGetLastError());
+  hipError_t e;
+  while ((e = hipEventQuery(c->done)) == hipErrorNotReady) {
+  }
+  HIP_TRY(c, e);
   std::memcpy(out, c->h_out, sizeof(float) * (size_t)c->L * c->B);
   return RTA_OK;
 }
@@ -756,6 +769,7 @@ int rta_query(rta_ctx* c, rta_info* info) {
   info->x_bytes_per_block = c->x_bytes;
   info->io_bytes_per_block = c->io_bytes;
   info->cmacs_per_block = c->cmacs;
+  info->tail_bytes_per_block = c->tail_bytes;
   info->grid = c->grid;
   info->outputs_per_group = c->G;
   info->rows_per_item = c->rows_per_item;
@@ -782,14 +796,22 @@ int rta_timing_read(rta_ctx* c, int64_t* blocks, double* mac_ms, double* final_m
   for (size_t i = 0; i + 3 <= c->events_used; i += 3) {
     float a = 0.f, b = 0.f;
     HIP_TRY(c, hipEventSynchronize(c->events[i + 2]));
-    HIP_TRY(c, hipEventElapsedTime(&a, c->events[i], c->events[i + 1]));
-    HIP_TRY(c, hipEventElapsedTime(&b, c->events[i + 1], c->events[i + 2]));
-    *mac_ms += a;
-    *final_ms += b;
+    HIP_TRY(c, hipEventElapsedTime(&a, c->events[i], c->events[i + 1]));      // k_head
+    HIP_TRY(c, hipEventElapsedTime(&b, c->events[i + 1], c->events[i + 2]));  // k_tail
+    *mac_ms += b;
+    *final_ms += a;
     *blocks += 1;
   }
   c->events_used = 0;
   return RTA_OK;
+}
+
+int rta_probe_read(const void* d_buf, int64_t bytes, int32_t grid, float* d_sink, void* stream) {
+  if (d_buf == nullptr || d_sink == nullptr || bytes < 16 || grid < 1) return RTA_E_ARG;
+  if ((reinterpret_cast<uintptr_t>(d_buf) & 15) != 0) return RTA_E_ARG;
+  hipLaunchKernelGGL(k_read_probe, dim3(grid), dim3(kThreads), 0, static_cast<hipStream_t>(stream),
+                     static_cast<const f32x4*>(d_buf), bytes / 16, d_sink);
+  return hipGetLastError() == hipSuccess ? RTA_OK : RTA_E_DEVICE;
 }
 
 int rta_destroy(rta_ctx* c) {

@@ -34,8 +34,8 @@ RTA_FLAG_NO_GRAPH = 0x2
 RTA_MAX_TIERS = 8
 
 EXPORTED = ("rta_create", "rta_process", "rta_process_device", "rta_reset",
-            "rta_query", "rta_timing_enable", "rta_timing_read", "rta_destroy",
-            "rta_strerror")
+            "rta_query", "rta_timing_enable", "rta_timing_read", "rta_probe_read",
+            "rta_destroy", "rta_strerror")
 
 
 class rta_scheme(ctypes.Structure):
@@ -60,6 +60,7 @@ class rta_info(ctypes.Structure):
                 ("x_bytes_per_block", ctypes.c_double),
                 ("io_bytes_per_block", ctypes.c_double),
                 ("cmacs_per_block", ctypes.c_double),
+                ("tail_bytes_per_block", ctypes.c_double),
                 ("grid", ctypes.c_int32),
                 ("outputs_per_group", ctypes.c_int32),
                 ("rows_per_item", ctypes.c_int32),
@@ -78,12 +79,14 @@ _lib.rta_reset.argtypes = [ctypes.c_void_p]
 _lib.rta_query.argtypes = [ctypes.c_void_p, ctypes.POINTER(rta_info)]
 _lib.rta_destroy.argtypes = [ctypes.c_void_p]
 _lib.rta_timing_enable.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+_lib.rta_probe_read.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
+                                ctypes.c_void_p]
 _lib.rta_timing_read.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
 _lib.rta_strerror.argtypes = [ctypes.c_int]
 _lib.rta_strerror.restype = ctypes.c_char_p
 for _f in ("rta_create", "rta_process", "rta_process_device", "rta_reset", "rta_query",
-           "rta_timing_enable", "rta_timing_read", "rta_destroy"):
+           "rta_timing_enable", "rta_timing_read", "rta_probe_read", "rta_destroy"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -186,6 +189,13 @@ def rta_timing_read(ctx):
     _check(_lib.rta_timing_read(ctx, ctypes.byref(n), ctypes.byref(a), ctypes.byref(b)),
            "rta_timing_read")
     return n.value, a.value, b.value
+
+
+def rta_probe_read(d_buf: int, nbytes: int, grid: int, d_sink: int, stream: int = 0) -> None:
+    """Launch the streaming-read probe (device pointers as ints)."""
+    _check(_lib.rta_probe_read(ctypes.c_void_p(d_buf), int(nbytes), int(grid),
+                               ctypes.c_void_p(d_sink), ctypes.c_void_p(stream or None)),
+           "rta_probe_read")
 
 
 def rta_destroy(ctx) -> None:
