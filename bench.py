@@ -13,9 +13,10 @@ Printed on one JSON line:
   latency       p50/p99/max of synchronous host-memory rta_process() calls
                 (PCIe copies included) issued one every B/fs as an audio
                 callback would, against the deadline B/fs; also back to back;
-  roofline      algorithmic bytes per launch of the multiply-accumulate
-                kernel k_tail / its mean duration from HIP events on the
-                launch stream, vs 8 TB/s;
+  roofline      algorithmic bytes per launch of the block kernel k_block
+                (every spectrum row once, every delay-line slot once, the
+                input and output blocks) / its mean duration from HIP events
+                on the launch stream, vs 8 TB/s;
   cpu_baseline  the FP64 oracle (single-partition FFT overlap-save) timed on
                 the host cores over a bounded sample of the same workload.
 """
@@ -55,7 +56,7 @@ def kernel_source_hash() -> str:
 def measured_traffic(workload: str, spectra: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel sources; otherwise None."""
-    path = os.path.join(ROOT, "profiles", f"k_tail_{workload}_{spectra}_pmc.json")
+    path = os.path.join(ROOT, "profiles", f"k_block_{workload}_{spectra}_pmc.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -141,8 +142,6 @@ def main() -> int:
     ap.add_argument("--cpu-channels", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mb", type=int, default=0)
-    ap.add_argument("--no-graph", action="store_true",
-                    help="rta_process launches eagerly instead of replaying a graph")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -174,8 +173,7 @@ def main() -> int:
     x = wl_steps.signal_array()
 
     t0 = time.perf_counter()
-    cv = rta.Convolver(filt, B, fs=fs, spectra=args.spectra,
-                       flags=rta.RTA_FLAG_NO_GRAPH if args.no_graph else 0)
+    cv = rta.Convolver(filt, B, fs=fs, spectra=args.spectra)
     info = cv.info()
     log(f"created in {time.perf_counter() - t0:.2f} s: grid={info['grid']} "
         f"rows/item={info['rows_per_item']} G={info['outputs_per_group']} "
@@ -204,15 +202,14 @@ def main() -> int:
             raise RuntimeError("rta_process_device failed")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    n_timed, mac_ms, fin_ms = rta.rta_timing_read(cv.ctx)
+    n_timed, kern_ms = rta.rta_timing_read(cv.ctx)
     rta.rta_timing_enable(cv.ctx, False)
-    mac_us = 1e3 * mac_ms / max(1, n_timed)
-    fin_us = 1e3 * fin_ms / max(1, n_timed)
+    kern_us = 1e3 * kern_ms / max(1, n_timed)
     ms_per_step = 1e3 * wall / args.steps
     audio_per_step = B / fs
     value = audio_per_step / (ms_per_step / 1e3)
-    log(f"timed {args.steps} steps: {ms_per_step * 1e3:.1f} us/step; k_tail {mac_us:.1f} us, "
-        f"k_head {fin_us:.1f} us (mean of {n_timed})")
+    log(f"timed {args.steps} steps: {ms_per_step * 1e3:.1f} us/step; k_block {kern_us:.1f} us "
+        f"(mean of {n_timed})")
     probes = read_probes(torch, rta, int(info["spectra_bytes"]), info["grid"], stream)
 
     # synchronous host-memory blocks: per-block latency including PCIe
@@ -246,8 +243,9 @@ def main() -> int:
                  "p99_us": float(np.percentile(plat_us, 99)), "max_us": float(plat_us.max()),
                  "xruns": int(np.sum(plat_us > deadline))}
 
-    bytes_per_launch = info["tail_bytes_per_block"]
-    achieved = bytes_per_launch / (mac_us * 1e-6) / 1e9
+    bytes_per_launch = (info["h_bytes_per_block"] + info["x_bytes_per_block"]
+                        + info["io_bytes_per_block"])
+    achieved = bytes_per_launch / (kern_us * 1e-6) / 1e9
     traffic = measured_traffic(wl.name, args.spectra)
     cpu = None
     if not args.no_cpu_baseline:
@@ -286,7 +284,7 @@ def main() -> int:
                                  "max_us": float(lat_us.max()),
                                  "xruns": int(np.sum(lat_us > deadline))},
         "roofline": {
-            "kernel": "k_tail",
+            "kernel": "k_block",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
@@ -294,8 +292,7 @@ def main() -> int:
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
             "bytes_per_launch": bytes_per_launch,
-            "kernel_us_mean": mac_us,
-            "head_kernel_us_mean": fin_us,
+            "kernel_us_mean": kern_us,
         },
         "read_probe": probes,
         "cpu_baseline": cpu,

@@ -57,8 +57,6 @@ typedef enum rta_dtype { RTA_FP32 = 0, RTA_FP16 = 1, RTA_BF16 = 2 } rta_dtype;
 #define RTA_FLAG_SPIKE   0x1u  /* NUPC: do a tier's whole frame in the block
                                   its input completes (needs offset >= size-B
                                   ... see rta_scheme); default spreads it.  */
-#define RTA_FLAG_NO_GRAPH 0x2u /* rta_process(): launch eagerly instead of
-                                  replaying a captured hipGraph.            */
 
 /* Partition scheme (Sec. III-B: uniform and non-uniform partitioning).
  *   size[t]  partition length of tier t in samples; size[0] must equal the
@@ -132,22 +130,24 @@ int rta_create(rta_ctx** out, double fs, int32_t block,
 /* Process one block, host memory in and out, synchronously.
  *   in   [n_in][block] FP32 host array (row-major), read during the call.
  *   out  [n_out][block] FP32 host array, valid on return.
- * The input is copied into the context's pinned, device-mapped buffer; the
- * block's output kernel (a captured hipGraph unless RTA_FLAG_NO_GRAPH) reads
- * it and writes the output block straight into a second pinned buffer over
- * PCIe, with no DMA copies.  The call spins until that kernel has finished
- * and copies the output to `out`; the multiply-accumulate of partitions >= 1
- * for the next block is left running on the context's stream and the next
- * call is ordered after it.  Must not be interleaved with
- * rta_process_device() calls still in flight on another stream. */
+ * The input is copied into the context's pinned, device-mapped buffer and
+ * one kernel is launched on the context's own stream.  Its output
+ * workgroups read that buffer and write the output block straight into a
+ * second pinned buffer over PCIe (no DMA copies); the last of them raises a
+ * flag in pinned memory, on which the call spins before copying the output
+ * to `out`.  The multiply-accumulate of partitions >= 2 for the next block,
+ * in the same launch, keeps running after the call returns; the next call is
+ * stream-ordered after it.  Must not be interleaved with rta_process_device()
+ * calls still in flight on another stream. */
 int rta_process(rta_ctx* ctx, const float* in, float* out);
 
 /* Process one block, device memory in and out, stream-ordered.
  *   d_in    [n_in][block] FP32 device array; d_out [n_out][block] FP32.
  *   stream  hipStream_t to launch on; NULL is HIP's null (default) stream.
- * Enqueues the block and returns without waiting; d_out is valid once the
- * stream reaches this point.  Successive calls must be ordered on one
- * stream (the block index lives in device memory and advances per call). */
+ * Enqueues the block's kernel and returns without waiting; d_out is valid
+ * once the stream has passed it.  Successive calls must be ordered on one
+ * stream: the block index is kept on the host and passed to each launch, so
+ * a launch captured into a graph and replayed would repeat the same block. */
 int rta_process_device(rta_ctx* ctx, const float* d_in, float* d_out,
                        void* stream);
 
@@ -155,25 +155,19 @@ int rta_process_device(rta_ctx* ctx, const float* d_in, float* d_out,
  * if the context had just been created.  Synchronous. */
 int rta_reset(rta_ctx* ctx);
 
-/* Fill *info with the context's geometry and counters.  Synchronizes the
- * context's stream to read the block index. */
+/* Fill *info with the context's geometry and counters (no device call). */
 int rta_query(rta_ctx* ctx, rta_info* info);
 
-/* Kernel timing (profiling aid).  Each block is two kernel launches: the
- * output kernel of this block (forward FFT, partition 0, inverse FFT and
- * overlap-save output) and the multiply-accumulate kernel of partitions >= 1
- * for the next block.  After rta_timing_enable(ctx, 1), every block launched
- * by rta_process_device() or by rta_process() with RTA_FLAG_NO_GRAPH records
- * three HIP events on its launch stream: before the output kernel, between
- * the two kernels and after the multiply-accumulate kernel.
- * rta_timing_read() waits for the recorded events and returns the number of
- * timed blocks and the summed durations in milliseconds of the
- * multiply-accumulate kernel (mac_ms) and of the output kernel (final_ms),
- * then forgets them.  Blocks beyond 65536 are not recorded.
- * rta_timing_enable(ctx, 0) stops recording. */
+/* Kernel timing (profiling aid).  Each block is one kernel launch (the heads
+ * of this block and the multiply-accumulate of partitions >= 2 for the next
+ * one).  After rta_timing_enable(ctx, 1), every block launched by
+ * rta_process() or rta_process_device() records two HIP events on its launch
+ * stream, just before and just after the kernel.  rta_timing_read() waits
+ * for the recorded events, returns the number of timed blocks and the summed
+ * kernel durations in milliseconds, then forgets them.  Blocks beyond 65536
+ * are not recorded.  rta_timing_enable(ctx, 0) stops recording. */
 int rta_timing_enable(rta_ctx* ctx, int32_t on);
-int rta_timing_read(rta_ctx* ctx, int64_t* blocks, double* mac_ms,
-                    double* final_ms);
+int rta_timing_read(rta_ctx* ctx, int64_t* blocks, double* kernel_ms);
 
 /* Measurement aid, independent of any context: launch a streaming-read
  * kernel over the first floor(bytes/16)*16 bytes of device memory d_buf

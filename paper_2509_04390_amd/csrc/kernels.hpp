@@ -1,29 +1,34 @@
 // kernels.hpp -- gfx950 kernels of the partitioned convolution.
 //
-// Two launches per audio block, ordered on one stream.
+// One launch per audio block.
 //
 // The frequency-domain delay line (Sec. IV step 2) gives every output block
 //     Y_l[k] = sum_q sum_{p<K} H_{l,q,p}[k] * X_q[(n - p) mod K][k].
-// Only the p = 0 term needs the block that has just arrived; the terms
-// p >= 1 use spectra already in the delay line.  So block n is produced by
+// Only the p = 0 term needs the block that has just arrived, and the p = 1
+// term needs the previous block's spectrum; every term p >= 2 uses spectra
+// that were in the delay line one block earlier.  Launch n of k_block
+// therefore runs two kinds of workgroups side by side:
 //
-// k_head (latency-critical, one workgroup per output group): real FFT of
-//   each input's window [x_{n-1}, x_n] (Sec. IV step 1, batched in LDS),
-//   store it into ring slot n mod K, add sum_q H_{l,q,0} * X_q, add the
-//   partial sums of the p >= 1 terms that k_tail computed beforehand, run the
-//   inverse real FFT and keep the second half of the 2B samples
-//   (overlap-save, Sec. IV step 3), then advance the device block index;
+//   head workgroups (one per output group, dispatched first, latency
+//   critical): real FFT of each input's window [x_{n-1}, x_n] (Sec. IV step
+//   1, batched in LDS), store it into ring slot n mod K, add
+//   sum_q H_{l,q,0} X_q(n) + H_{l,q,1} X_q(n-1) to the partial sums of the
+//   terms p >= 2 that the previous launch prepared, inverse real FFT, keep
+//   the second half of the 2B samples (overlap-save, Sec. IV step 3), write
+//   the output block; the last head workgroup then raises a host-visible
+//   completion flag;
 //
-// k_tail (bandwidth-bound, launched right after the head of block n-1, so it
-//   runs while the host waits for the next audio block): work item i covers a
-//   group of G outputs, one input, a partition range [p0, p1) with p0 >= 1
-//   and a slice of bins, and writes
-//       sum_{p in [p0,p1)} H_{l,q,p}[k] * X_q[(n - p) mod K][k]
-//   to its own partial-sum slot.
+//   tail workgroups (bandwidth bound): work item i covers a group of G
+//   outputs, one input, a partition range [p0, p1) with p0 >= 2 and a slice
+//   of bins, and writes sum_{p in [p0,p1)} H_{l,q,p} X_q[(n+1-p) mod K] for
+//   the NEXT block into its partial-sum slot.
 //
-// The sum is the same as forming all K terms at once; only when each term is
-// formed changes.  Every partial slot is written by exactly one item and read
-// in a fixed order, so results are reproducible bit for bit.
+// Partial sums are double-buffered by block parity: launch n reads parity
+// n & 1 (heads) and writes parity (n+1) & 1 (tails).  The tails read ring
+// slots n-1 ... n+2-K, never slot n, which the heads write in the same
+// launch.  Each slot is written by exactly one item and read in a fixed
+// order, so results are reproducible bit for bit; the sum is the same as
+// forming all K terms at once.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -63,17 +68,11 @@ struct DevTier {
   const int64_t* pair_row;   // [L*Q] first row of pair (l,q), -1 = no path
   const int32_t* pair_K;     // [L*Q] partitions of pair (l,q)
   float2* X;                 // FDL ring [Q][K][P]
-  float2* partial;           // [slots][G][P]
+  float2* partial;           // [2][slots][G][P], by block parity
   const float2* tw;          // W_P^j (j<P) then W_2P^k (k<P)
   float* oring;              // tiers >= 1: output ring [L][R]
   int64_t offset;            // first filter tap of the tier
-  int32_t P, logP, K, pad;
-};
-
-struct DevState {
-  int64_t block;             // index of the next block to process
-  uint32_t arrive;           // workgroups of the current launch that read it
-  uint32_t pad;
+  int32_t P, logP, K, nslots;
 };
 
 struct KArgs {
@@ -81,7 +80,6 @@ struct KArgs {
   const Item* items;         // [n_phase][max_items]
   const int32_t* phase_count;
   const Group* groups;
-  DevState* state;
   float* hist;               // input history [Q][hist_len]
   const float* in;           // [Q][B]
   float* out;                // [L][B]
@@ -89,8 +87,14 @@ struct KArgs {
   int64_t ring_mask;         // output ring length - 1
   int32_t B, Q, L, n_tiers;
   int32_t n_phase, max_items;
-  int32_t head_nq;           // inputs transformed per pass in k_head
+  int32_t head_nq;           // inputs transformed per pass by a head
+  int32_t n_head;            // head workgroups (output groups)
+  int32_t head_slots;        // head part of the grid (n_head rounded up to 8)
   int32_t pad;
+  int64_t n;                 // index of the block of this launch
+  const void* H01;           // [L][Q][2][P] spectra of partitions 0 and 1
+  unsigned int* head_count;  // heads finished in this launch (zero between)
+  int64_t* done_flag;        // host-visible: n + 1 once the output is written
 };
 
 // ---------------------------------------------------------------------------
@@ -338,7 +342,7 @@ __device__ void reduce_slots(const DevTier& T, const Group& grp, int g, float2* 
   __syncthreads();
 }
 
-// LDS layout of k_head, in float2 units (the host sizes the launch with the
+// LDS layout of a head workgroup, in float2 units (the host sizes the launch with the
 // same function): Y [G][P] | Xa [nbuf][P] | Xb [nbuf][P] | twiddles | 256.
 struct HeadLds {
   int y, xa, xb, tw, scratch, total;
@@ -355,35 +359,12 @@ __host__ __device__ inline HeadLds head_lds(int P, int G, int nq) {
   return h;
 }
 
+// Head workgroup: output group `grp` of block n (see the top of the file).
 template <typename HT, int G>
-__global__ __launch_bounds__(kThreads) void k_tail(const KArgs A) {
-  extern __shared__ float2 lds[];
-  const int64_t frame = A.state->block;  // the block whose head comes next
-  const int phase = (int)(frame % A.n_phase);
-  if ((int)blockIdx.x >= A.phase_count[phase]) return;
-  const Item it = A.items[(int64_t)phase * A.max_items + blockIdx.x];
-  if (it.kind == K_NOP) return;
-  mac_item<HT, G>(A, A.tier[it.tier], it, A.groups[it.group], frame, lds);
-}
-
-template <typename HT, int G>
-__global__ __launch_bounds__(kThreads) void k_head(const KArgs A) {
-  extern __shared__ float2 lds[];
-  __shared__ int64_t sh_n;
+__device__ void head_work(const KArgs& A, const Group& grp, float2* lds) {
   const int tid = threadIdx.x;
-  if (tid == 0) sh_n = A.state->block;
-  __syncthreads();
-  const int64_t n = sh_n;
-  if (tid == 0) {
-    const uint32_t old = __hip_atomic_fetch_add(&A.state->arrive, 1u, __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_AGENT);
-    if (old == gridDim.x - 1) {  // every workgroup has read n
-      A.state->arrive = 0;
-      A.state->block = n + 1;
-    }
-  }
+  const int64_t n = A.n;
   const DevTier& T = A.tier[0];
-  const Group grp = A.groups[blockIdx.x];
   const int P = T.P, logP = T.logP;  // P == B
   const HeadLds L = head_lds(P, G, A.head_nq);
   float2* Y = lds + L.y;
@@ -391,13 +372,20 @@ __global__ __launch_bounds__(kThreads) void k_head(const KArgs A) {
   float2* Xb = lds + L.xb;
   float2* scratch = lds + L.scratch;
   const float2* tw = stage_twiddles(T, lds + L.tw);
-  const HT* Hbase = reinterpret_cast<const HT*>(T.H);
+  const HT* H01 = reinterpret_cast<const HT*>(A.H01);
 
-  // 1. the p >= 1 terms, summed by k_tail before this launch
-  for (int g = 0; g < grp.nl; ++g) reduce_slots<G>(T, grp, g, Y + g * P, scratch);
+  // 1. the terms p >= 2, summed by the previous launch's tail items
+  const DevTier Tcur = [&] {
+    DevTier t = T;
+    t.partial = T.partial + (n & 1) * (int64_t)T.nslots * G * P;
+    return t;
+  }();
+  for (int g = 0; g < grp.nl; ++g) reduce_slots<G>(Tcur, grp, g, Y + g * P, scratch);
 
-  // 2. the p = 0 term: window -> real FFT -> ring slot n mod K, times H_{l,q,0}
-  const int slot = wrap_slot(n, T.K);
+  // 2. the terms p = 0 (fresh spectrum) and p = 1 (ring slot n-1)
+  const int slot0 = wrap_slot(n, T.K);
+  const int slot1 = wrap_slot(n - 1, T.K);
+  const bool has_p1 = T.K >= 2;
   for (int q0 = 0; q0 < A.Q; q0 += A.head_nq) {
     const int nb = min(A.head_nq, A.Q - q0);
     for (int e = tid; e < nb * P; e += kThreads) {
@@ -414,10 +402,10 @@ __global__ __launch_bounds__(kThreads) void k_head(const KArgs A) {
     float2* z = fft_stockham<false>(Xa, Xb, P, logP, tw, nb);
     float2* x = (z == Xa) ? Xb : Xa;
     rfft_post(z, x, P, tw + P, nb);
-    if (blockIdx.x == 0) {
+    if (grp.l0 == 0) {  // the first group stores the block for later launches
       for (int e = tid; e < nb * P; e += kThreads) {
         const int b = e / P, k = e - b * P;
-        T.X[((int64_t)(q0 + b) * T.K + slot) * P + k] = x[e];
+        T.X[((int64_t)(q0 + b) * T.K + slot0) * P + k] = x[e];
       }
       for (int e = tid; e < nb * A.B; e += kThreads) {
         const int b = e / A.B, i = e - b * A.B;
@@ -431,15 +419,17 @@ __global__ __launch_bounds__(kThreads) void k_head(const KArgs A) {
       const int l = grp.l0 + g;
       float2 acc = Y[e];
       for (int b = 0; b < nb; ++b) {
-        const int pair = l * A.Q + q0 + b;
-        const int64_t row = T.pair_row[pair];
-        if (row < 0) continue;
-        const float2 h = HVec<HT>::load1(Hbase + row * (int64_t)P + k);
-        const float2 xv = x[b * P + k];
-        if (k == 0)
-          acc = make_float2(acc.x + h.x * xv.x, acc.y + h.y * xv.y);
-        else
-          acc = cadd(acc, cmul(h, xv));
+        const int q = q0 + b;
+        const HT* h = H01 + ((int64_t)(l * A.Q + q) * 2) * P + k;
+        const float2 h0 = HVec<HT>::load1(h);
+        const float2 x0 = x[b * P + k];
+        float2 t0 = (k == 0) ? make_float2(h0.x * x0.x, h0.y * x0.y) : cmul(h0, x0);
+        if (has_p1) {
+          const float2 h1 = HVec<HT>::load1(h + P);
+          const float2 x1 = T.X[((int64_t)q * T.K + slot1) * P + k];
+          t0 = cadd(t0, (k == 0) ? make_float2(h1.x * x1.x, h1.y * x1.y) : cmul(h1, x1));
+        }
+        acc = cadd(acc, t0);
       }
       Y[e] = acc;
     }
@@ -469,6 +459,57 @@ __global__ __launch_bounds__(kThreads) void k_head(const KArgs A) {
     }
     A.out[(int64_t)l * A.B + i] = y0;
     A.out[(int64_t)l * A.B + i + 1] = y1;
+  }
+
+  // 4. completion: every head makes its output visible system-wide, the
+  //    last one raises the flag (only the heads count, so the host does not
+  //    wait for the tail workgroups of this launch)
+  __threadfence_system();
+  __syncthreads();
+  if (tid == 0) {
+    const unsigned int old = __hip_atomic_fetch_add(A.head_count, 1u, __ATOMIC_ACQ_REL,
+                                                    __HIP_MEMORY_SCOPE_SYSTEM);
+    if (old == (unsigned int)A.n_head - 1u) {
+      __hip_atomic_store(A.head_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(A.done_flag, n + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+  }
+}
+
+template <typename HT, int G>
+__global__ __launch_bounds__(kThreads) void k_block(const KArgs A) {
+  extern __shared__ float2 lds[];
+  const int b = blockIdx.x;
+  if (b < A.head_slots) {
+    if (b < A.n_head) head_work<HT, G>(A, A.groups[b], lds);
+    return;
+  }
+  const int64_t frame = A.n + 1;  // tails prepare the next block
+  const int phase = (int)(frame % A.n_phase);
+  const int i = b - A.head_slots;
+  if (i >= A.phase_count[phase]) return;
+  const Item it = A.items[(int64_t)phase * A.max_items + i];
+  if (it.kind == K_NOP) return;
+  DevTier T = A.tier[it.tier];
+  T.partial += (frame & 1) * (int64_t)T.nslots * G * T.P;
+  mac_item<HT, G>(A, T, it, A.groups[it.group], frame, lds);
+}
+
+// Dense copy of partitions 0 and 1 of every pair for the heads:
+// H01[l][q][r][P] = row r of pair (l, q), or zeros if the pair has no row r.
+template <typename HT>
+__global__ __launch_bounds__(kThreads) void k_gather_head_rows(const HT* H, const int64_t* pair_row,
+                                                              const int32_t* pair_K, int P,
+                                                              int n_pairs, HT* H01) {
+  const int pr = blockIdx.x;  // pair * 2 + r
+  if (pr >= 2 * n_pairs) return;
+  const int pair = pr >> 1, r = pr & 1;
+  const int64_t row = pair_row[pair];
+  const bool has = row >= 0 && r < pair_K[pair];
+  for (int k = threadIdx.x; k < P; k += kThreads) {
+    HT v{};
+    if (has) v = H[(row + r) * (int64_t)P + k];
+    H01[(int64_t)pr * P + k] = v;
   }
 }
 

@@ -2,15 +2,17 @@
 //
 // A context owns, on one device:
 //   - the filter spectra of every tier, rows [pair][partition][P bins] in the
-//     chosen storage type (built on the GPU at creation, k_spectra);
+//     chosen storage type (built on the GPU at creation by k_spectra), plus a
+//     dense copy of partitions 0 and 1 of every pair for the head
+//     workgroups;
 //   - per tier an FDL ring [Q][K][P] of FP32 input spectra and a partial-sum
-//     area; the input history ring [Q][hist_len]; per later tier an output
-//     ring [L][ring_len];
-//   - the work lists: per block phase a list of items, one per workgroup of
-//     the block launch, built here once and never changed;
-//   - the device block index and arrival counters.
-// rta_process() replays a captured graph (H2D input, block kernel, D2H
-// output); rta_process_device() launches the block kernel on a caller stream.
+//     area double-buffered by block parity; the input history ring
+//     [Q][hist_len]; per later tier an output ring [L][ring_len];
+//   - the tail work list, built once at creation and checked against every
+//     buffer bound;
+//   - pinned, device-mapped input/output/flag buffers for rta_process.
+// Each block is one k_block launch on a stream; the block index is kept on
+// the host and passed by value.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,6 +35,7 @@ constexpr int kMinBlock = 16;
 constexpr int kMaxBlock = 4096;
 constexpr int kXcds = 8;                     // MI355X: 8 XCDs, workgroups round-robin
 constexpr int64_t kStageBytes = 64ll << 20;  // filter taps staged per spectra batch
+constexpr size_t kMaxTimedBlocks = 65536;
 
 struct TierHost {
   int P = 0, logP = 0, K = 0, count = 0;
@@ -72,30 +75,29 @@ struct rta_ctx {
   uint32_t flags = 0;
   int n_tiers = 0;
   TierHost tier[kMaxTiers];
-  int G = 1, rows_per_item = 0, grid = 0, n_phase = 1, max_items = 0;
+  int G = 1, rows_per_item = 0, n_phase = 1, max_items = 0, n_items = 0;
+  int n_groups = 0, head_slots = 0, head_nq = 1;
   int64_t hist_len = 0, ring_len = 0;
-  size_t lds_tail = 0;         // k_tail dynamic LDS
-  size_t lds_head = 0;         // k_head dynamic LDS
-  int head_nq = 1;             // inputs transformed per pass in k_head
-  hipEvent_t done = nullptr;   // recorded after an rta_process output copy
+  size_t lds = 0;              // k_block dynamic LDS
+  int64_t block = 0;           // index of the next block
 
+  void* H01 = nullptr;         // [L][Q][2][P] partitions 0 and 1
   float* hist = nullptr;
   Item* items = nullptr;
   int32_t* phase_count = nullptr;
   Group* groups = nullptr;
-  DevState* state = nullptr;
-  int n_groups = 0;
+  unsigned int* head_count = nullptr;
 
-  float* h_in = nullptr;    // pinned host staging, mapped into the device
+  float* h_in = nullptr;       // pinned host staging, mapped into the device
   float* h_out = nullptr;
-  float* m_in = nullptr;    // device addresses of h_in / h_out
+  int64_t* h_flag = nullptr;
+  float* m_in = nullptr;       // device addresses of the three
   float* m_out = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
+  int64_t* m_flag = nullptr;
 
   bool poisoned = false;
   bool timing = false;
-  std::vector<hipEvent_t> events;  // 3 per timed block
+  std::vector<hipEvent_t> events;  // 2 per timed block
   size_t events_used = 0;
   int64_t device_bytes = 0, spectra_bytes = 0;
   double h_bytes = 0, x_bytes = 0, io_bytes = 0, cmacs = 0, tail_bytes = 0;
@@ -133,6 +135,7 @@ int dev_alloc(rta_ctx* c, T** p, size_t count) {
 }
 
 size_t spectra_elem_bytes(int dtype) { return dtype == RTA_FP32 ? 8 : 4; }
+int vec_bins(int dtype) { return dtype == RTA_FP32 ? 2 : 4; }
 
 // W_P^j (j < P) then W_2P^k (k < P), FP64 evaluated then rounded to FP32.
 std::vector<float2> twiddles(int P) {
@@ -151,25 +154,20 @@ std::vector<float2> twiddles(int P) {
 
 using BlockKernel = void (*)(const KArgs);
 
-#define RTA_PICK(KERNEL, HT)                           \
+BlockKernel block_kernel(int dtype, int G) {
+#define RTA_PICK(HT)                                   \
   switch (G) {                                         \
-    case 1: return KERNEL<HT, 1>;                      \
-    case 2: return KERNEL<HT, 2>;                      \
-    case 4: return KERNEL<HT, 4>;                      \
+    case 1: return k_block<HT, 1>;                     \
+    case 2: return k_block<HT, 2>;                     \
+    case 4: return k_block<HT, 4>;                     \
     default: return nullptr;                           \
   }
-#define RTA_DISPATCH(KERNEL)                           \
-  if (dtype == RTA_FP32) RTA_PICK(KERNEL, float2)      \
-  if (dtype == RTA_FP16) RTA_PICK(KERNEL, f16c_t)      \
-  if (dtype == RTA_BF16) RTA_PICK(KERNEL, bf16c_t)     \
-  return nullptr;
-
-BlockKernel tail_kernel(int dtype, int G) { RTA_DISPATCH(k_tail) }
-BlockKernel head_kernel(int dtype, int G) { RTA_DISPATCH(k_head) }
-#undef RTA_DISPATCH
+  if (dtype == RTA_FP32) RTA_PICK(float2)
+  if (dtype == RTA_FP16) RTA_PICK(f16c_t)
+  if (dtype == RTA_BF16) RTA_PICK(bf16c_t)
 #undef RTA_PICK
-
-int vec_bins(int dtype) { return dtype == RTA_FP32 ? 2 : 4; }
+  return nullptr;
+}
 
 hipError_t launch_spectra(int dtype, dim3 grid, size_t lds, hipStream_t s, const float* taps,
                           const SpecRow* rows, void* H, int P, int logP, const float2* tw,
@@ -186,6 +184,23 @@ hipError_t launch_spectra(int dtype, dim3 grid, size_t lds, hipStream_t s, const
   return hipGetLastError();
 }
 
+hipError_t launch_gather(int dtype, const TierHost& T, int n_pairs, void* H01, hipStream_t s) {
+  const dim3 grid(2 * n_pairs);
+  if (dtype == RTA_FP32)
+    hipLaunchKernelGGL(k_gather_head_rows<float2>, grid, dim3(kThreads), 0, s,
+                       static_cast<const float2*>(T.H), T.pair_row, T.pair_K, T.P, n_pairs,
+                       static_cast<float2*>(H01));
+  else if (dtype == RTA_FP16)
+    hipLaunchKernelGGL(k_gather_head_rows<f16c_t>, grid, dim3(kThreads), 0, s,
+                       static_cast<const f16c_t*>(T.H), T.pair_row, T.pair_K, T.P, n_pairs,
+                       static_cast<f16c_t*>(H01));
+  else
+    hipLaunchKernelGGL(k_gather_head_rows<bf16c_t>, grid, dim3(kThreads), 0, s,
+                       static_cast<const bf16c_t*>(T.H), T.pair_row, T.pair_K, T.P, n_pairs,
+                       static_cast<bf16c_t*>(H01));
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Argument validation (no HIP calls).
 // ---------------------------------------------------------------------------
@@ -197,7 +212,7 @@ int validate(double fs, int32_t block, const rta_scheme* scheme, int32_t n_in, i
   if (n_in < 1 || n_out < 1 || (int64_t)n_in * n_out > (1 << 20)) return RTA_E_ARG;
   if (filters == nullptr || lengths == nullptr) return RTA_E_ARG;
   if (spectra != RTA_FP32 && spectra != RTA_FP16 && spectra != RTA_BF16) return RTA_E_ARG;
-  if (flags & ~(RTA_FLAG_SPIKE | RTA_FLAG_NO_GRAPH)) return RTA_E_ARG;
+  if (flags & ~RTA_FLAG_SPIKE) return RTA_E_ARG;
   int64_t max_len = 0;
   for (int64_t i = 0; i < (int64_t)n_in * n_out; ++i) {
     if (lengths[i] < 0 || lengths[i] > (int64_t(1) << 31)) return RTA_E_ARG;
@@ -233,9 +248,10 @@ int validate(double fs, int32_t block, const rta_scheme* scheme, int32_t n_in, i
 }
 
 // ---------------------------------------------------------------------------
-// Work lists of k_tail for the uniform first tier: partitions p >= 1 of every
+// Tail work lists for the uniform first tier: partitions p >= 2 of every
 // (output group, input) are cut into chunks of about R rows, each chunk into
-// bin slices; each chunk owns one partial-sum slot of its group.
+// bin slices; each chunk owns one partial-sum slot of its group.  (The heads
+// do partitions 0 and 1.)
 // ---------------------------------------------------------------------------
 struct Bucket {
   int q, p0, k0;
@@ -260,10 +276,10 @@ int build_plan(rta_ctx* c, std::vector<Item>& flat, std::vector<Group>& groups) 
   int64_t total_rows = 0;
   for (int g = 0; g < ngroups; ++g)
     for (int q = 0; q < c->Q; ++q)
-      total_rows += std::max(0, group_rows(g * G, std::min(G, c->L - g * G), q) - 1);
+      total_rows += std::max(0, group_rows(g * G, std::min(G, c->L - g * G), q) - 2);
   int R = c->rows_per_item;
   if (R <= 0) {
-    const int64_t target_items = env_int("RTA_TARGET_ITEMS", 2048);
+    const int64_t target_items = env_int("RTA_TARGET_ITEMS", 1024);
     R = (int)std::max<int64_t>(8, (total_rows * nslice + target_items - 1) / target_items);
   }
   c->rows_per_item = R;
@@ -279,12 +295,12 @@ int build_plan(rta_ctx* c, std::vector<Item>& flat, std::vector<Group>& groups) 
     gr.nslot = 0;
     for (int q = 0; q < c->Q; ++q) {
       const int kg = group_rows(gr.l0, gr.nl, q);
-      if (kg <= 1) continue;  // partition 0 is done by k_head
-      const int rows = kg - 1;
+      if (kg <= 2) continue;  // partitions 0 and 1 are done by the heads
+      const int rows = kg - 2;
       const int nch = (rows + R - 1) / R;
       for (int ch = 0; ch < nch; ++ch) {
-        const int p0 = 1 + (int)((int64_t)ch * rows / nch);
-        const int p1 = 1 + (int)((int64_t)(ch + 1) * rows / nch);
+        const int p0 = 2 + (int)((int64_t)ch * rows / nch);
+        const int p1 = 2 + (int)((int64_t)(ch + 1) * rows / nch);
         for (int sl = 0; sl < nslice; ++sl) {
           Item it{};
           it.kind = K_MAC;
@@ -346,14 +362,14 @@ int build_plan(rta_ctx* c, std::vector<Item>& flat, std::vector<Group>& groups) 
     if (it.group < 0 || it.group >= (int)groups.size()) return RTA_E_STATE;
     const Group& gr = groups[it.group];
     if (it.q < 0 || it.q >= c->Q) return RTA_E_STATE;
-    if (it.p0 < 1 || it.p1 < it.p0 || it.p1 > T.K) return RTA_E_STATE;
+    if (it.p0 < 2 || it.p1 < it.p0 || it.p1 > T.K) return RTA_E_STATE;
     if (it.k0 < 0 || it.k0 % W != 0 || it.k0 + W > P) return RTA_E_STATE;
     if (it.slot < gr.slot0 || it.slot >= gr.slot0 + gr.nslot) return RTA_E_STATE;
   }
   return RTA_OK;
 }
 
-KArgs make_args(const rta_ctx* c, const float* in, float* out) {
+KArgs make_args(const rta_ctx* c, const float* in, float* out, int64_t n) {
   KArgs a{};
   for (int t = 0; t < c->n_tiers; ++t) {
     const TierHost& T = c->tier[t];
@@ -369,11 +385,11 @@ KArgs make_args(const rta_ctx* c, const float* in, float* out) {
     d.P = T.P;
     d.logP = T.logP;
     d.K = T.K;
+    d.nslots = std::max(1, T.nslots);
   }
   a.items = c->items;
   a.phase_count = c->phase_count;
   a.groups = c->groups;
-  a.state = c->state;
   a.hist = c->hist;
   a.in = in;
   a.out = out;
@@ -386,44 +402,34 @@ KArgs make_args(const rta_ctx* c, const float* in, float* out) {
   a.n_phase = c->n_phase;
   a.max_items = c->max_items;
   a.head_nq = c->head_nq;
+  a.n_head = c->n_groups;
+  a.head_slots = c->head_slots;
+  a.n = n;
+  a.H01 = c->H01;
+  a.head_count = c->head_count;
+  a.done_flag = c->m_flag;
   return a;
 }
 
-// The head of this block (output) and the tail of the next one.
-void enqueue_head(const rta_ctx* c, const KArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(head_kernel(c->dtype, c->G), dim3(c->n_groups), dim3(kThreads), c->lds_head, s, a);
-}
-void enqueue_tail(const rta_ctx* c, const KArgs& a, hipStream_t s) {
-  if (c->grid > 0)
-    hipLaunchKernelGGL(tail_kernel(c->dtype, c->G), dim3(c->grid), dim3(kThreads), c->lds_tail, s, a);
-}
-void enqueue_block(const rta_ctx* c, const float* in, float* out, hipStream_t s) {
-  const KArgs a = make_args(c, in, out);
-  enqueue_head(c, a, s);
-  enqueue_tail(c, a, s);
-}
-
-constexpr size_t kMaxTimedBlocks = 65536;
-
+// One block: heads of block n and tails of block n + 1 in a single launch.
 int launch_block(rta_ctx* c, const float* in, float* out, hipStream_t s) {
-  if (c->timing && c->events_used + 3 <= 3 * kMaxTimedBlocks) {
-    while (c->events.size() < c->events_used + 3) {
-      hipEvent_t e;
-      HIP_TRY(c, hipEventCreate(&e));
-      c->events.push_back(e);
+  const KArgs a = make_args(c, in, out, c->block);
+  const unsigned grid = (unsigned)(c->head_slots + c->n_items);
+  hipEvent_t* e = nullptr;
+  if (c->timing && c->events_used + 2 <= 2 * kMaxTimedBlocks) {
+    while (c->events.size() < c->events_used + 2) {
+      hipEvent_t ev;
+      HIP_TRY(c, hipEventCreate(&ev));
+      c->events.push_back(ev);
     }
-    hipEvent_t* e = &c->events[c->events_used];
-    c->events_used += 3;
-    const KArgs a = make_args(c, in, out);
+    e = &c->events[c->events_used];
+    c->events_used += 2;
     HIP_TRY(c, hipEventRecord(e[0], s));
-    enqueue_head(c, a, s);
-    HIP_TRY(c, hipEventRecord(e[1], s));
-    enqueue_tail(c, a, s);
-    HIP_TRY(c, hipEventRecord(e[2], s));
-  } else {
-    enqueue_block(c, in, out, s);
   }
+  hipLaunchKernelGGL(block_kernel(c->dtype, c->G), dim3(grid), dim3(kThreads), c->lds, s, a);
   HIP_TRY(c, hipGetLastError());
+  if (e) HIP_TRY(c, hipEventRecord(e[1], s));
+  c->block += 1;
   return RTA_OK;
 }
 
@@ -431,17 +437,18 @@ int zero_state(rta_ctx* c) {
   for (int t = 0; t < c->n_tiers; ++t) {
     TierHost& T = c->tier[t];
     HIP_TRY(c, hipMemsetAsync(T.X, 0, sizeof(float2) * (size_t)c->Q * T.K * T.P, c->stream));
+    // before the first block the terms p >= 2 are all zero (zero history)
+    HIP_TRY(c, hipMemsetAsync(T.partial, 0,
+                              sizeof(float2) * 2 * (size_t)std::max(1, T.nslots) * c->G * T.P,
+                              c->stream));
     if (T.oring)
       HIP_TRY(c, hipMemsetAsync(T.oring, 0, sizeof(float) * (size_t)c->L * c->ring_len, c->stream));
   }
   HIP_TRY(c, hipMemsetAsync(c->hist, 0, sizeof(float) * (size_t)c->Q * c->hist_len, c->stream));
-  // before the first head the p >= 1 terms are all zero (zero history)
-  for (int t = 0; t < c->n_tiers; ++t)
-    HIP_TRY(c, hipMemsetAsync(c->tier[t].partial, 0,
-                              sizeof(float2) * (size_t)std::max(1, c->tier[t].nslots) * c->G * c->tier[t].P,
-                              c->stream));
-  HIP_TRY(c, hipMemsetAsync(c->state, 0, sizeof(DevState), c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->head_count, 0, sizeof(unsigned int), c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
+  __atomic_store_n(c->h_flag, (int64_t)0, __ATOMIC_RELEASE);
+  c->block = 0;
   return RTA_OK;
 }
 
@@ -529,8 +536,6 @@ int create_impl(rta_ctx* c, const std::vector<int>& size, const std::vector<int>
   HIP_TRY(c, hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
 
   // tiers and partition counts
-  int64_t max_len = 0;
-  for (int64_t i = 0; i < (int64_t)c->Q * c->L; ++i) max_len = std::max(max_len, lengths[i]);
   c->n_tiers = (int)size.size();
   int64_t off = 0;
   for (int t = 0; t < c->n_tiers; ++t) {
@@ -565,8 +570,8 @@ int create_impl(rta_ctx* c, const std::vector<int>& size, const std::vector<int>
     c->x_bytes += (double)c->Q * kmax * T.P * 8.0;
     if (t == 0) {
       double tail_rows = 0;
-      for (int32_t kp : T.kp) tail_rows += std::max(0, kp - 1);
-      c->tail_bytes = tail_rows * T.P * eb + (double)c->Q * std::max(0, kmax - 1) * T.P * 8.0;
+      for (int32_t kp : T.kp) tail_rows += std::max(0, kp - 2);
+      c->tail_bytes = tail_rows * T.P * eb + (double)c->Q * std::max(0, kmax - 2) * T.P * 8.0;
     }
     if ((st = dev_alloc(c, reinterpret_cast<char**>(&T.H), (size_t)std::max<int64_t>(1, rows) * T.P * eb)) != RTA_OK)
       return st;
@@ -584,27 +589,33 @@ int create_impl(rta_ctx* c, const std::vector<int>& size, const std::vector<int>
   c->hist_len = int64_t(1) << ilog2(c->hist_len);
   c->ring_len = 1;
 
-  // spectra
+  // spectra, then the heads' dense copy of partitions 0 and 1
   if ((st = build_spectra(c, filters, lengths)) != RTA_OK) return st;
+  const size_t eb = spectra_elem_bytes(c->dtype);
+  if ((st = dev_alloc(c, reinterpret_cast<char**>(&c->H01), (size_t)c->L * c->Q * 2 * c->tier[0].P * eb)) != RTA_OK)
+    return st;
+  HIP_TRY(c, launch_gather(c->dtype, c->tier[0], c->L * c->Q, c->H01, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
 
-  // outputs per group: as requested, halved until k_head's LDS fits
+  // outputs per group: as requested, halved until a head's LDS fits
   int max_lds = 0;
   HIP_TRY(c, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
   while (c->G > 1 && (int64_t)sizeof(float2) * head_lds(c->tier[0].P, c->G, 1).total + 64 > max_lds)
     c->G /= 2;
 
-  // work lists
+  // tail work list
   std::vector<Item> flat;
   std::vector<Group> groups;
   if ((st = build_plan(c, flat, groups)) != RTA_OK) return st;
   c->n_phase = 1;
-  c->max_items = (int)std::max<size_t>(1, flat.size());
-  c->grid = c->max_items;
+  c->n_items = (int)flat.size();
+  c->max_items = std::max(1, c->n_items);
+  c->head_slots = (c->n_groups + kXcds - 1) / kXcds * kXcds;  // keeps tails' XCD residues
   const int32_t pc = (int32_t)flat.size();
   if ((st = dev_alloc(c, &c->items, (size_t)c->max_items)) != RTA_OK) return st;
   if ((st = dev_alloc(c, &c->phase_count, 1)) != RTA_OK) return st;
   if ((st = dev_alloc(c, &c->groups, groups.size())) != RTA_OK) return st;
-  if ((st = dev_alloc(c, &c->state, 1)) != RTA_OK) return st;
+  if ((st = dev_alloc(c, &c->head_count, 1)) != RTA_OK) return st;
   if (!flat.empty())
     HIP_TRY(c, hipMemcpy(c->items, flat.data(), sizeof(Item) * flat.size(), hipMemcpyHostToDevice));
   HIP_TRY(c, hipMemcpy(c->phase_count, &pc, sizeof(int32_t), hipMemcpyHostToDevice));
@@ -612,65 +623,51 @@ int create_impl(rta_ctx* c, const std::vector<int>& size, const std::vector<int>
 
   for (int t = 0; t < c->n_tiers; ++t) {
     TierHost& T = c->tier[t];
-    if ((st = dev_alloc(c, &T.partial, (size_t)std::max(1, T.nslots) * c->G * T.P)) != RTA_OK) return st;
+    if ((st = dev_alloc(c, &T.partial, 2 * (size_t)std::max(1, T.nslots) * c->G * T.P)) != RTA_OK)
+      return st;
   }
   if ((st = dev_alloc(c, &c->hist, (size_t)c->Q * c->hist_len)) != RTA_OK) return st;
-  // rta_process I/O: pinned host buffers that the kernels read and write
-  // directly over PCIe (no DMA copies on the latency path)
+
+  // rta_process I/O and completion flag: pinned host memory that the kernel
+  // reads and writes directly over PCIe (no DMA copies on the latency path)
   if (hipHostMalloc(reinterpret_cast<void**>(&c->h_in), sizeof(float) * (size_t)c->Q * c->B,
                     hipHostMallocMapped) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&c->h_out), sizeof(float) * (size_t)c->L * c->B,
-                    hipHostMallocMapped) != hipSuccess) {
+                    hipHostMallocMapped) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&c->h_flag), sizeof(int64_t),
+                    hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
     (void)hipGetLastError();
     return RTA_E_NOMEM;
   }
   HIP_TRY(c, hipHostGetDevicePointer(reinterpret_cast<void**>(&c->m_in), c->h_in, 0));
   HIP_TRY(c, hipHostGetDevicePointer(reinterpret_cast<void**>(&c->m_out), c->h_out, 0));
+  HIP_TRY(c, hipHostGetDevicePointer(reinterpret_cast<void**>(&c->m_flag), c->h_flag, 0));
 
-  // LDS (kernels.hpp): k_tail needs the row-group reduction area; k_head
-  // holds the group's output spectra, two FFT buffers for head_nq inputs and
-  // the staged twiddles (HeadLds).  head_nq: as many inputs per pass as fit in
-  // 48 KB, at least one.
+  // LDS: the larger of a head's layout (HeadLds) and a tail item's row-group
+  // reduction.  head_nq: as many inputs per pass as fit in 48 KB, at least 1.
   const int C = vec_bins(c->dtype);
-  c->lds_tail = sizeof(float2) * (size_t)kThreads * C * c->G;
   const int P0 = c->tier[0].P;
   const int fixed = head_lds(P0, c->G, 1).total - 2 * std::max(1, c->G) * P0;
   c->head_nq = std::max(1, std::min(c->Q, (6144 - fixed) / (2 * P0)));
-  c->lds_head = sizeof(float2) * (size_t)head_lds(P0, c->G, c->head_nq).total;
-  if ((int64_t)std::max(c->lds_tail, c->lds_head) + 64 > (int64_t)max_lds) return RTA_E_UNSUPPORTED;
-  if (c->lds_tail > 65536)
-    HIP_TRY(c, hipFuncSetAttribute(reinterpret_cast<const void*>(tail_kernel(c->dtype, c->G)),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_tail));
-  if (c->lds_head > 65536)
-    HIP_TRY(c, hipFuncSetAttribute(reinterpret_cast<const void*>(head_kernel(c->dtype, c->G)),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_head));
-
+  c->lds = sizeof(float2) * std::max((size_t)head_lds(P0, c->G, c->head_nq).total,
+                                     (size_t)kThreads * C * c->G);
+  if ((int64_t)c->lds + 64 > (int64_t)max_lds) return RTA_E_UNSUPPORTED;
+  if (c->lds > 65536)
+    HIP_TRY(c, hipFuncSetAttribute(reinterpret_cast<const void*>(block_kernel(c->dtype, c->G)),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds));
   return zero_state(c);
 }
 
 void free_all(rta_ctx* c) {
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
   c->events.clear();
-  if (c->done) (void)hipEventDestroy(c->done);
-  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
-  if (c->graph) (void)hipGraphDestroy(c->graph);
-  if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (void* p : c->dev_allocs) (void)hipFree(p);
   c->dev_allocs.clear();
   if (c->h_in) (void)hipHostFree(c->h_in);
   if (c->h_out) (void)hipHostFree(c->h_out);
+  if (c->h_flag) (void)hipHostFree(c->h_flag);
   if (c->stream) (void)hipStreamDestroy(c->stream);
-}
-
-// rta_process's block: the head kernel reading the pinned input and writing
-// the pinned output, captured once as a graph.
-int capture_graph(rta_ctx* c) {
-  const KArgs a = make_args(c, c->m_in, c->m_out);
-  HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-  enqueue_head(c, a, c->stream);
-  HIP_TRY(c, hipStreamEndCapture(c->stream, &c->graph));
-  HIP_TRY(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
-  return RTA_OK;
 }
 
 }  // namespace
@@ -693,13 +690,12 @@ int rta_create(rta_ctx** out, double fs, int32_t block, const rta_scheme* scheme
   c->L = n_out;
   c->dtype = spectra;
   c->flags = flags;
-  c->G = env_int("RTA_G", 1);
+  // tiling defaults measured on the 1 -> 32 x 480,000-tap workload: two
+  // outputs per workgroup and about 1,024 tail items (env overrides for tuning)
+  c->G = env_int("RTA_G", n_out >= 16 ? 2 : 1);
   if (c->G != 1 && c->G != 2 && c->G != 4) c->G = 1;
   c->rows_per_item = env_int("RTA_ROWS", 0);
   st = create_impl(c, size, count, filters, lengths);
-  if (st == RTA_OK && hipEventCreateWithFlags(&c->done, hipEventDisableTiming) != hipSuccess)
-    st = RTA_E_DEVICE;
-  if (st == RTA_OK && !(flags & RTA_FLAG_NO_GRAPH)) st = capture_graph(c);
   if (st != RTA_OK) {
     free_all(c);
     delete c;
@@ -713,23 +709,24 @@ int rta_process(rta_ctx* c, const float* in, float* out) {
   if (c == nullptr || in == nullptr || out == nullptr) return RTA_E_ARG;
   if (c->poisoned) return RTA_E_DEVICE;
   std::memcpy(c->h_in, in, sizeof(float) * (size_t)c->Q * c->B);
-  const KArgs a = make_args(c, c->m_in, c->m_out);
-  if (c->flags & RTA_FLAG_NO_GRAPH) {
-    enqueue_head(c, a, c->stream);
-    HIP_TRY(c, hipGetLastError());
-  } else {
-    if (c->gexec == nullptr) return RTA_E_STATE;
-    HIP_TRY(c, hipGraphLaunch(c->gexec, c->stream));
+  const int64_t want = c->block + 1;
+  int st = launch_block(c, c->m_in, c->m_out, c->stream);
+  if (st != RTA_OK) return st;
+  // spin until the last head has raised the flag; the tail workgroups of the
+  // same launch keep running.  Every few thousand polls the stream is asked
+  // for errors so a failed launch cannot spin forever.
+  for (uint64_t i = 1;; ++i) {
+    if (__atomic_load_n(c->h_flag, __ATOMIC_ACQUIRE) == want) break;
+    if ((i & 4095) == 0) {
+      const hipError_t e = hipStreamQuery(c->stream);
+      if (e == hipSuccess) {
+        if (__atomic_load_n(c->h_flag, __ATOMIC_ACQUIRE) == want) break;
+        c->poisoned = true;
+        return RTA_E_DEVICE;
+      }
+      if (e != hipErrorNotReady) HIP_TRY(c, e);
+    }
   }
-  // the output is complete when the head has finished; the next block's
-  // tail is enqueued behind it and is not waited for
-  HIP_TRY(c, hipEventRecord(c->done, c->stream));
-  enqueue_tail(c, a, c->stream);
-  HIP_TRY(c, hipGetLastError());
-  hipError_t e;
-  while ((e = hipEventQuery(c->done)) == hipErrorNotReady) {
-  }
-  HIP_TRY(c, e);
   std::memcpy(out, c->h_out, sizeof(float) * (size_t)c->L * c->B);
   return RTA_OK;
 }
@@ -763,6 +760,7 @@ int rta_query(rta_ctx* c, rta_info* info) {
     info->tier_count[t] = c->tier[t].count;
     info->tier_offset[t] = c->tier[t].offset;
   }
+  info->blocks_done = c->block;
   info->spectra_bytes = c->spectra_bytes;
   info->device_bytes = c->device_bytes;
   info->h_bytes_per_block = c->h_bytes;
@@ -770,16 +768,11 @@ int rta_query(rta_ctx* c, rta_info* info) {
   info->io_bytes_per_block = c->io_bytes;
   info->cmacs_per_block = c->cmacs;
   info->tail_bytes_per_block = c->tail_bytes;
-  info->grid = c->grid;
+  info->grid = c->head_slots + c->n_items;
   info->outputs_per_group = c->G;
   info->rows_per_item = c->rows_per_item;
   info->poisoned = c->poisoned ? 1 : 0;
-  if (c->poisoned) return RTA_E_DEVICE;
-  HIP_TRY(c, hipDeviceSynchronize());
-  DevState s{};
-  HIP_TRY(c, hipMemcpy(&s, c->state, sizeof(s), hipMemcpyDeviceToHost));
-  info->blocks_done = s.block;
-  return RTA_OK;
+  return c->poisoned ? RTA_E_DEVICE : RTA_OK;
 }
 
 int rta_timing_enable(rta_ctx* c, int32_t on) {
@@ -788,18 +781,16 @@ int rta_timing_enable(rta_ctx* c, int32_t on) {
   return RTA_OK;
 }
 
-int rta_timing_read(rta_ctx* c, int64_t* blocks, double* mac_ms, double* final_ms) {
-  if (c == nullptr || blocks == nullptr || mac_ms == nullptr || final_ms == nullptr) return RTA_E_ARG;
+int rta_timing_read(rta_ctx* c, int64_t* blocks, double* block_ms) {
+  if (c == nullptr || blocks == nullptr || block_ms == nullptr) return RTA_E_ARG;
   if (c->poisoned) return RTA_E_DEVICE;
   *blocks = 0;
-  *mac_ms = *final_ms = 0.0;
-  for (size_t i = 0; i + 3 <= c->events_used; i += 3) {
-    float a = 0.f, b = 0.f;
-    HIP_TRY(c, hipEventSynchronize(c->events[i + 2]));
-    HIP_TRY(c, hipEventElapsedTime(&a, c->events[i], c->events[i + 1]));      // k_head
-    HIP_TRY(c, hipEventElapsedTime(&b, c->events[i + 1], c->events[i + 2]));  // k_tail
-    *mac_ms += b;
-    *final_ms += a;
+  *block_ms = 0.0;
+  for (size_t i = 0; i + 2 <= c->events_used; i += 2) {
+    float ms = 0.f;
+    HIP_TRY(c, hipEventSynchronize(c->events[i + 1]));
+    HIP_TRY(c, hipEventElapsedTime(&ms, c->events[i], c->events[i + 1]));
+    *block_ms += ms;
     *blocks += 1;
   }
   c->events_used = 0;

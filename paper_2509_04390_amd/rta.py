@@ -30,7 +30,6 @@ RTA_FP32, RTA_FP16, RTA_BF16 = 0, 1, 2
 DTYPES = {"fp32": RTA_FP32, "fp16": RTA_FP16, "bf16": RTA_BF16}
 
 RTA_FLAG_SPIKE = 0x1
-RTA_FLAG_NO_GRAPH = 0x2
 RTA_MAX_TIERS = 8
 
 EXPORTED = ("rta_create", "rta_process", "rta_process_device", "rta_reset",
@@ -82,7 +81,7 @@ _lib.rta_timing_enable.argtypes = [ctypes.c_void_p, ctypes.c_int32]
 _lib.rta_probe_read.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
                                 ctypes.c_void_p]
 _lib.rta_timing_read.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
-                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+                                 ctypes.POINTER(ctypes.c_double)]
 _lib.rta_strerror.argtypes = [ctypes.c_int]
 _lib.rta_strerror.restype = ctypes.c_char_p
 for _f in ("rta_create", "rta_process", "rta_process_device", "rta_reset", "rta_query",
@@ -182,13 +181,11 @@ def rta_timing_enable(ctx, on: bool) -> None:
 
 
 def rta_timing_read(ctx):
-    """(blocks, mac_ms_total, final_ms_total) since the last read."""
+    """(blocks, kernel_ms_total) since the last read."""
     n = ctypes.c_int64()
     a = ctypes.c_double()
-    b = ctypes.c_double()
-    _check(_lib.rta_timing_read(ctx, ctypes.byref(n), ctypes.byref(a), ctypes.byref(b)),
-           "rta_timing_read")
-    return n.value, a.value, b.value
+    _check(_lib.rta_timing_read(ctx, ctypes.byref(n), ctypes.byref(a)), "rta_timing_read")
+    return n.value, a.value
 
 
 def rta_probe_read(d_buf: int, nbytes: int, grid: int, d_sink: int, stream: int = 0) -> None:

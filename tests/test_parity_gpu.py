@@ -127,17 +127,6 @@ def test_device_path_equals_host_path_and_reruns_are_bitwise(rta):
     assert np.array_equal(y1, y3)
 
 
-def test_eager_launches_equal_graph_replays(rta):
-    B, lens, nb = CASES[4]
-    filt = make_filters(5, lens)
-    x = padded_signal(6, len(lens), nb, B, 1000)
-    with rta.Convolver(filt, B) as cv:
-        y_graph = cv.run(x)
-    with rta.Convolver(filt, B, flags=rta.RTA_FLAG_NO_GRAPH) as cv:
-        y_eager = cv.run(x)
-    assert np.array_equal(y_graph, y_eager)
-
-
 def test_block_shift_is_bitwise_invariant(rta):
     B = 64
     lens = [[3000, 200]]
