@@ -42,7 +42,13 @@ constexpr int kThreads = 256;
 constexpr int kMaxTiers = 8;
 constexpr int kUnroll = 4;
 
-enum ItemKind : int32_t { K_MAC = 0, K_NOP = 1 };
+enum ItemKind : int32_t {
+  K_MAC = 0,    // k_block tail: multiply-accumulate of a partition range
+  K_NOP = 1,    // padding
+  K_FFT = 2,    // k_tier: real FFT of a later tier's input frame into its ring
+  K_FINAL = 3   // k_tier: reduce + inverse FFT of a later tier's frame into its
+                // output ring
+};
 
 struct Item {          // one workgroup's work in one block (48 bytes)
   int32_t kind;        // ItemKind
@@ -54,7 +60,8 @@ struct Item {          // one workgroup's work in one block (48 bytes)
   int32_t k0;          // first bin of the slice
   int32_t slot;        // partial-sum slot (tier-local)
   int32_t target;      // items of this group launched in this block
-  int32_t lag;         // tiers >= 1: blocks since the frame's input completed
+  int32_t lag;         // tiers >= 1: launch index minus the block in which
+                       // the frame's input completed
   int32_t pad;
 };
 
@@ -71,8 +78,10 @@ struct DevTier {
   float2* partial;           // [2][slots][G][P], by block parity
   const float2* tw;          // W_P^j (j<P) then W_2P^k (k<P)
   float* oring;              // tiers >= 1: output ring [L][R]
-  int64_t offset;            // first filter tap of the tier
+  int64_t offset;            // first filter tap of the tier (o_t)
   int32_t P, logP, K, nslots;
+  int32_t r;                 // P / B: blocks per frame
+  int32_t pad2;
 };
 
 struct KArgs {
@@ -92,6 +101,12 @@ struct KArgs {
   int32_t head_slots;        // head part of the grid (n_head rounded up to 8)
   int32_t pad;
   int64_t n;                 // index of the block of this launch
+  const Item* tier_items;    // k_tier lists [n_phase][max_tier_items]
+  const int32_t* tier_count; // items per phase
+  const int32_t* tier_slot0; // [tier][group] first partial slot of later tiers
+  const int32_t* tier_nslot; // [tier][group] partial slots of later tiers
+  int32_t max_tier_items;
+  int32_t n_groups_total;
   const void* H01;           // [L][Q][2][P] spectra of partitions 0 and 1
   unsigned int* head_count;  // heads finished in this launch (zero between)
   int64_t* done_flag;        // host-visible: n + 1 once the output is written
@@ -484,15 +499,95 @@ __global__ __launch_bounds__(kThreads) void k_block(const KArgs A) {
     if (b < A.n_head) head_work<HT, G>(A, A.groups[b], lds);
     return;
   }
-  const int64_t frame = A.n + 1;  // tails prepare the next block
-  const int phase = (int)(frame % A.n_phase);
+  const int phase = (int)(A.n % A.n_phase);
   const int i = b - A.head_slots;
   if (i >= A.phase_count[phase]) return;
   const Item it = A.items[(int64_t)phase * A.max_items + i];
   if (it.kind == K_NOP) return;
   DevTier T = A.tier[it.tier];
-  T.partial += (frame & 1) * (int64_t)T.nslots * G * T.P;
+  int64_t frame;
+  if (it.tier == 0) {
+    frame = A.n + 1;  // first-tier tails prepare the next block
+    T.partial += (frame & 1) * (int64_t)T.nslots * G * T.P;
+  } else {
+    // later tier: the frame whose input completed in block n - lag
+    frame = (A.n - it.lag + 1) / T.r - 1;
+  }
   mac_item<HT, G>(A, T, it, A.groups[it.group], frame, lds);
+}
+
+// ---------------------------------------------------------------------------
+// Later tiers (non-uniform partitioning, Sec. III-B): partitions of P_t = r B
+// samples covering filter taps [o_t, o_t + K_t P_t).  Frame f of the tier is
+// input samples [f P_t, (f+1) P_t), complete after block n_f = (f+1) r - 1.
+// Its contribution y[f P_t + o_t + i] (i < P_t) is the second half of the
+// 2 P_t-point inverse FFT of sum_q sum_p H_{t,l,q,p} X_{t,q}(f - p), i.e. the
+// tier's delay o_t is realized in the time domain through the output ring.
+// k_tier runs after k_block on the same stream in the blocks that have
+// tier work: K_FFT items transform frame f into ring slot f mod K_t (in
+// block n_f), K_FINAL items reduce the partial sums that k_block's tail
+// items accumulated over the following blocks, inverse-FFT and store the
+// P_t output samples into the tier's output ring, where the heads of later
+// blocks add them.  LDS: two P_t-bin buffers, the twiddles if they fit, and
+// 256 float2 of reduction scratch.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline int tier_lds(int P) { return 2 * P + tw_lds_len(P) + kThreads; }
+
+template <int G>
+__global__ __launch_bounds__(kThreads) void k_tier(const KArgs A) {
+  extern __shared__ float2 lds[];
+  const int phase = (int)(A.n % A.n_phase);
+  const int i = blockIdx.x;
+  if (i >= A.tier_count[phase]) return;
+  const Item it = A.tier_items[(int64_t)phase * A.max_tier_items + i];
+  if (it.kind != K_FFT && it.kind != K_FINAL) return;
+  const DevTier& T = A.tier[it.tier];
+  const int P = T.P, logP = T.logP;
+  const int tid = threadIdx.x;
+  float2* a = lds;
+  float2* b = lds + P;
+  float2* scratch = lds + 2 * P + tw_lds_len(P);
+  const float2* tw = stage_twiddles(T, lds + 2 * P);
+  const int64_t nf = A.n - it.lag;          // block in which the frame completed
+  const int64_t f = (nf + 1) / T.r - 1;     // the frame
+
+  if (it.kind == K_FFT) {
+    // window: the last 2 P_t input samples up to the end of block nf
+    const float* hq = A.hist + (int64_t)it.q * (A.hist_mask + 1);
+    const int64_t start = (nf + 1) * A.B - 2 * (int64_t)P;
+    for (int m = tid; m < P; m += kThreads)
+      a[m] = make_float2(hq[(start + 2 * m) & A.hist_mask], hq[(start + 2 * m + 1) & A.hist_mask]);
+    __syncthreads();
+    float2* z = fft_stockham<false>(a, b, P, logP, tw);
+    float2* x = (z == a) ? b : a;
+    rfft_post(z, x, P, tw + P);
+    float2* dst = T.X + ((int64_t)it.q * T.K + wrap_slot(f, T.K)) * P;
+    for (int k = tid; k < P; k += kThreads) dst[k] = x[k];
+    return;
+  }
+
+  // K_FINAL: one output group of frame f
+  const Group grp = A.groups[it.group];
+  const float scale = 1.0f / (float)(2 * P);
+  for (int g = 0; g < grp.nl; ++g) {
+    const int l = grp.l0 + g;
+    Group tg = grp;  // this tier's partial slots of the group
+    tg.slot0 = A.tier_slot0[(int64_t)it.tier * A.n_groups_total + it.group];
+    tg.nslot = A.tier_nslot[(int64_t)it.tier * A.n_groups_total + it.group];
+    reduce_slots<G>(T, tg, g, a, scratch);
+    irfft_pre(a, b, P, tw + P);
+    float2* z = fft_stockham<true>(b, a, P, logP, tw);
+    float* ring = T.oring + (int64_t)l * (A.ring_mask + 1);
+    const int64_t y0 = f * (int64_t)P + T.offset;  // first output sample of the frame
+    const int half = P >> 1;
+    for (int m = half + tid; m < P; m += kThreads) {
+      const float2 v = z[m];
+      const int64_t i0 = 2 * (int64_t)(m - half);
+      ring[(y0 + i0) & A.ring_mask] = v.x * scale;
+      ring[(y0 + i0 + 1) & A.ring_mask] = v.y * scale;
+    }
+    __syncthreads();
+  }
 }
 
 // Dense copy of partitions 0 and 1 of every pair for the heads:

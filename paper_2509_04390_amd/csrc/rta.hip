@@ -82,6 +82,13 @@ struct rta_ctx {
   int64_t block = 0;           // index of the next block
 
   void* H01 = nullptr;         // [L][Q][2][P] partitions 0 and 1
+  Item* tier_items = nullptr;  // k_tier lists [n_phase][max_tier_items]
+  int32_t* tier_count = nullptr;
+  int32_t* tier_slot0 = nullptr;
+  int32_t* tier_nslot = nullptr;
+  int max_tier_items = 0;
+  std::vector<int32_t> tier_count_host;  // k_tier items per phase
+  size_t lds_tier = 0;         // k_tier dynamic LDS
   float* hist = nullptr;
   Item* items = nullptr;
   int32_t* phase_count = nullptr;
@@ -169,6 +176,15 @@ BlockKernel block_kernel(int dtype, int G) {
   return nullptr;
 }
 
+BlockKernel tier_kernel(int G) {
+  switch (G) {
+    case 1: return k_tier<1>;
+    case 2: return k_tier<2>;
+    case 4: return k_tier<4>;
+    default: return nullptr;
+  }
+}
+
 hipError_t launch_spectra(int dtype, dim3 grid, size_t lds, hipStream_t s, const float* taps,
                           const SpecRow* rows, void* H, int P, int logP, const float2* tw,
                           int* range) {
@@ -239,100 +255,56 @@ int validate(double fs, int32_t block, const rta_scheme* scheme, int32_t n_in, i
     if (!is_pow2(size[t]) || size[t] % block != 0 || size[t] > (1 << 13)) return RTA_E_ARG;
     if (t > 0 && size[t] <= size[t - 1]) return RTA_E_ARG;
     if (count[t] < 0 || (count[t] == 0 && t != T - 1)) return RTA_E_ARG;
-    if (t > 0 && off < 2 * (int64_t)size[t] - block) return RTA_E_ARG;
+    // a later tier's frame needs one block for its FFT and at least one for
+    // its multiply-accumulate before its first output sample is due
+    if (t > 0 && off < (int64_t)size[t] + block) return RTA_E_ARG;
     off += (int64_t)count[t] * size[t];
   }
   if (count[T - 1] > 0 && max_len > off) return RTA_E_ARG;
-  if (T > 1) return RTA_E_UNSUPPORTED;  // later tiers: not built yet
   return RTA_OK;
 }
 
 // ---------------------------------------------------------------------------
-// Tail work lists for the uniform first tier: partitions p >= 2 of every
-// (output group, input) are cut into chunks of about R rows, each chunk into
-// bin slices; each chunk owns one partial-sum slot of its group.  (The heads
-// do partitions 0 and 1.)
+// Work lists.  The block index n selects phase n mod n_phase (n_phase =
+// P_max / B).  k_block's list for a phase holds
+//   - the first tier's tail items (every phase): partitions p >= 2 of every
+//     (output group, input), cut into chunks of about R rows and bin slices;
+//     each chunk owns one partial slot of its group (the heads do p = 0, 1);
+//   - the multiply-accumulate items of later tiers whose frame is being
+//     accumulated in that block.
+// k_tier's list for a phase holds the later tiers' FFT items (in the block a
+// frame's input completes) and their final items (in the block after the
+// frame's last multiply-accumulate).  Tier t (P_t = r B, offset o_t) gives a
+// frame s = (o_t + B - P_t) / B blocks between input completion and first
+// output; its multiply-accumulate is spread over nmac = min(s, r + 1) - 1
+// blocks (1 with RTA_FLAG_SPIKE).
 // ---------------------------------------------------------------------------
 struct Bucket {
-  int q, p0, k0;
+  int tier, q, p0, k0;
   std::vector<Item> items;
   int64_t rows = 0;
 };
 
-int build_plan(rta_ctx* c, std::vector<Item>& flat, std::vector<Group>& groups) {
-  TierHost& T = c->tier[0];
-  const int P = T.P;
-  const int C = vec_bins(c->dtype);
-  const int W = std::min(P, kThreads * C);
-  const int nslice = P / W;
-  const int G = c->G;
-  const int ngroups = (c->L + G - 1) / G;
-  auto group_rows = [&](int l0, int nl, int q) {
-    int kg = 0;
-    for (int l = l0; l < l0 + nl; ++l) kg = std::max(kg, T.kp[l * c->Q + q]);
-    return kg;
-  };
+struct Plan {
+  std::vector<std::vector<Item>> block;  // per phase: k_block tail items
+  std::vector<std::vector<Item>> tier;   // per phase: k_tier items
+  std::vector<Group> groups;
+  std::vector<int32_t> tier_slot0, tier_nslot;  // [tier][group]
+};
 
-  int64_t total_rows = 0;
-  for (int g = 0; g < ngroups; ++g)
-    for (int q = 0; q < c->Q; ++q)
-      total_rows += std::max(0, group_rows(g * G, std::min(G, c->L - g * G), q) - 2);
-  int R = c->rows_per_item;
-  if (R <= 0) {
-    const int64_t target_items = env_int("RTA_TARGET_ITEMS", 1024);
-    R = (int)std::max<int64_t>(8, (total_rows * nslice + target_items - 1) / target_items);
-  }
-  c->rows_per_item = R;
+// nmac of tier t >= 1 (see above)
+int tier_nmac(const rta_ctx* c, int t) {
+  const TierHost& T = c->tier[t];
+  const int r = T.P / c->B;
+  const int64_t s = (T.offset + c->B - T.P) / c->B;
+  if (c->flags & RTA_FLAG_SPIKE) return 1;
+  return (int)std::min<int64_t>(s, r + 1) - 1;
+}
 
-  std::vector<Bucket> buckets;
-  groups.clear();
-  int slot = 0;
-  for (int g = 0; g < ngroups; ++g) {
-    Group gr;
-    gr.l0 = g * G;
-    gr.nl = std::min(G, c->L - gr.l0);
-    gr.slot0 = slot;
-    gr.nslot = 0;
-    for (int q = 0; q < c->Q; ++q) {
-      const int kg = group_rows(gr.l0, gr.nl, q);
-      if (kg <= 2) continue;  // partitions 0 and 1 are done by the heads
-      const int rows = kg - 2;
-      const int nch = (rows + R - 1) / R;
-      for (int ch = 0; ch < nch; ++ch) {
-        const int p0 = 2 + (int)((int64_t)ch * rows / nch);
-        const int p1 = 2 + (int)((int64_t)(ch + 1) * rows / nch);
-        for (int sl = 0; sl < nslice; ++sl) {
-          Item it{};
-          it.kind = K_MAC;
-          it.tier = 0;
-          it.group = g;
-          it.q = q;
-          it.p0 = p0;
-          it.p1 = p1;
-          it.k0 = sl * W;
-          it.slot = slot;
-          auto bit = std::find_if(buckets.begin(), buckets.end(), [&](const Bucket& b) {
-            return b.q == q && b.p0 == p0 && b.k0 == it.k0;
-          });
-          if (bit == buckets.end()) {
-            buckets.push_back(Bucket{q, p0, it.k0, {}, 0});
-            bit = buckets.end() - 1;
-          }
-          bit->items.push_back(it);
-          bit->rows += (int64_t)(p1 - p0) * gr.nl;
-        }
-        ++slot;
-        ++gr.nslot;
-      }
-    }
-    groups.push_back(gr);
-  }
-  T.nslots = slot;
-  c->n_groups = (int)groups.size();
-
-  // XCD-aware placement: a bucket's items (same input, partitions and bins,
-  // different outputs) all get list positions with the same residue mod 8, so
-  // they run on one XCD and its delay-line rows are fetched into one L2.
+// XCD-aware placement: a bucket's items (same tier, input, partitions and
+// bins; different outputs) all get list positions with the same residue
+// mod 8, so they run on one XCD and fetch their delay-line rows into one L2.
+std::vector<Item> place_on_xcds(std::vector<Bucket>& buckets) {
   std::vector<std::vector<Item>> xl(kXcds);
   std::vector<int64_t> load(kXcds, 0);
   std::stable_sort(buckets.begin(), buckets.end(),
@@ -344,27 +316,217 @@ int build_plan(rta_ctx* c, std::vector<Item>& flat, std::vector<Group>& groups) 
   }
   size_t longest = 0;
   for (auto& v : xl) longest = std::max(longest, v.size());
-  flat.assign(longest * kXcds, Item{});
+  std::vector<Item> flat(longest * kXcds, Item{});
   for (auto& it : flat) it.kind = K_NOP;
   for (int x = 0; x < kXcds; ++x)
     for (size_t i = 0; i < xl[x].size(); ++i) flat[i * kXcds + x] = xl[x][i];
   while (!flat.empty() && flat.back().kind == K_NOP) flat.pop_back();
+  return flat;
+}
+
+void add_to_bucket(std::vector<Bucket>& buckets, const Item& it, int nl) {
+  auto bit = std::find_if(buckets.begin(), buckets.end(), [&](const Bucket& b) {
+    return b.tier == it.tier && b.q == it.q && b.p0 == it.p0 && b.k0 == it.k0;
+  });
+  if (bit == buckets.end()) {
+    buckets.push_back(Bucket{it.tier, it.q, it.p0, it.k0, {}, 0});
+    bit = buckets.end() - 1;
+  }
+  bit->items.push_back(it);
+  bit->rows += (int64_t)(it.p1 - it.p0) * nl;
+}
+
+int build_plan(rta_ctx* c, Plan& plan) {
+  const int G = c->G;
+  const int C = vec_bins(c->dtype);
+  const int ngroups = (c->L + G - 1) / G;
+  const int n_phase = c->tier[c->n_tiers - 1].P / c->B;
+  c->n_phase = n_phase;
+  plan.block.assign(n_phase, {});
+  plan.tier.assign(n_phase, {});
+  plan.groups.clear();
+  plan.tier_slot0.assign((size_t)kMaxTiers * ngroups, 0);
+  plan.tier_nslot.assign((size_t)kMaxTiers * ngroups, 0);
+  for (int g = 0; g < ngroups; ++g) {
+    Group gr{};
+    gr.l0 = g * G;
+    gr.nl = std::min(G, c->L - gr.l0);
+    plan.groups.push_back(gr);
+  }
+  auto group_rows = [&](const TierHost& T, const Group& gr, int q) {
+    int kg = 0;
+    for (int l = gr.l0; l < gr.l0 + gr.nl; ++l) kg = std::max(kg, T.kp[l * c->Q + q]);
+    return kg;
+  };
+
+  // ---- first tier: partitions >= 2, every phase
+  std::vector<Item> tier0;
+  {
+    TierHost& T = c->tier[0];
+    const int P = T.P, W = std::min(P, kThreads * C), nslice = P / W;
+    int64_t total_rows = 0;
+    for (const Group& gr : plan.groups)
+      for (int q = 0; q < c->Q; ++q) total_rows += std::max(0, group_rows(T, gr, q) - 2);
+    int R = c->rows_per_item;
+    if (R <= 0) {
+      const int64_t target_items = env_int("RTA_TARGET_ITEMS", 1024);
+      R = (int)std::max<int64_t>(8, (total_rows * nslice + target_items - 1) / target_items);
+    }
+    c->rows_per_item = R;
+    int slot = 0;
+    for (int g = 0; g < ngroups; ++g) {
+      Group& gr = plan.groups[g];
+      gr.slot0 = slot;
+      gr.nslot = 0;
+      for (int q = 0; q < c->Q; ++q) {
+        const int kg = group_rows(T, gr, q);
+        if (kg <= 2) continue;  // partitions 0 and 1 are done by the heads
+        const int rows = kg - 2;
+        const int nch = (rows + R - 1) / R;
+        for (int ch = 0; ch < nch; ++ch) {
+          const int p0 = 2 + (int)((int64_t)ch * rows / nch);
+          const int p1 = 2 + (int)((int64_t)(ch + 1) * rows / nch);
+          for (int sl = 0; sl < nslice; ++sl) {
+            Item it{};
+            it.kind = K_MAC;
+            it.tier = 0;
+            it.group = g;
+            it.q = q;
+            it.p0 = p0;
+            it.p1 = p1;
+            it.k0 = sl * W;
+            it.slot = slot;
+            tier0.push_back(it);
+          }
+          ++slot;
+          ++gr.nslot;
+        }
+      }
+    }
+    T.nslots = slot;
+  }
+
+  // ---- later tiers
+  std::vector<std::vector<Item>> tier_mac(n_phase);
+  for (int t = 1; t < c->n_tiers; ++t) {
+    TierHost& T = c->tier[t];
+    const int P = T.P, W = std::min(P, kThreads * C), nslice = P / W;
+    const int r = P / c->B;
+    const int nmac = tier_nmac(c, t);
+    if (nmac < 1) return RTA_E_STATE;
+    const int R = std::max(1, env_int("RTA_TIER_ROWS", 16));
+    struct Chunk { int g, q, p0, p1, slot; };
+    std::vector<Chunk> chunks;
+    int slot = 0;
+    for (int g = 0; g < ngroups; ++g) {
+      const Group& gr = plan.groups[g];
+      plan.tier_slot0[(size_t)t * ngroups + g] = slot;
+      for (int q = 0; q < c->Q; ++q) {
+        const int kg = group_rows(T, gr, q);
+        if (kg == 0) continue;
+        const int nch = (kg + R - 1) / R;
+        for (int ch = 0; ch < nch; ++ch)
+          chunks.push_back(Chunk{g, q, (int)((int64_t)ch * kg / nch),
+                                 (int)((int64_t)(ch + 1) * kg / nch), slot++});
+      }
+      plan.tier_nslot[(size_t)t * ngroups + g] = slot - plan.tier_slot0[(size_t)t * ngroups + g];
+    }
+    T.nslots = slot;
+    // spread the chunks over the nmac blocks, balancing rows
+    int64_t total = 0;
+    for (const Chunk& ch : chunks) total += ch.p1 - ch.p0;
+    std::vector<int> when(chunks.size(), 0);
+    int64_t acc = 0;
+    for (size_t i = 0; i < chunks.size(); ++i) {
+      when[i] = total > 0 ? (int)std::min<int64_t>(nmac - 1, acc * nmac / total) : 0;
+      acc += chunks[i].p1 - chunks[i].p0;
+    }
+    for (int ph0 = r - 1; ph0 < n_phase; ph0 += r) {  // phases in which a frame completes
+      for (int q = 0; q < c->Q; ++q) {
+        bool used = false;
+        for (int l = 0; l < c->L; ++l) used |= T.kp[l * c->Q + q] > 0;
+        if (!used) continue;
+        Item it{};
+        it.kind = K_FFT;
+        it.tier = t;
+        it.q = q;
+        it.lag = 0;
+        plan.tier[ph0].push_back(it);
+      }
+      for (size_t i = 0; i < chunks.size(); ++i) {
+        const int lag = 1 + when[i];
+        for (int sl = 0; sl < nslice; ++sl) {
+          Item it{};
+          it.kind = K_MAC;
+          it.tier = t;
+          it.group = chunks[i].g;
+          it.q = chunks[i].q;
+          it.p0 = chunks[i].p0;
+          it.p1 = chunks[i].p1;
+          it.k0 = sl * W;
+          it.slot = chunks[i].slot;
+          it.lag = lag;
+          tier_mac[(ph0 + lag) % n_phase].push_back(it);
+        }
+      }
+      for (int g = 0; g < ngroups; ++g) {
+        if (plan.tier_nslot[(size_t)t * ngroups + g] == 0) continue;
+        Item it{};
+        it.kind = K_FINAL;
+        it.tier = t;
+        it.group = g;
+        it.lag = nmac;
+        plan.tier[(ph0 + nmac) % n_phase].push_back(it);
+      }
+    }
+  }
+  c->n_groups = ngroups;
+
+  // ---- per-phase k_block lists, XCD-aware
+  for (int ph = 0; ph < n_phase; ++ph) {
+    std::vector<Bucket> buckets;
+    for (const Item& it : tier0) add_to_bucket(buckets, it, plan.groups[it.group].nl);
+    for (const Item& it : tier_mac[ph]) add_to_bucket(buckets, it, plan.groups[it.group].nl);
+    plan.block[ph] = place_on_xcds(buckets);
+  }
 
   // every index the kernels derive from an item must stay inside the
   // buffers allocated for this plan
-  for (const Group& gr : groups)
+  for (const Group& gr : plan.groups)
     if (gr.l0 < 0 || gr.nl < 1 || gr.nl > G || gr.l0 + gr.nl > c->L || gr.slot0 < 0 ||
-        gr.nslot < 0 || gr.slot0 + gr.nslot > T.nslots)
+        gr.nslot < 0 || gr.slot0 + gr.nslot > c->tier[0].nslots)
       return RTA_E_STATE;
-  for (const Item& it : flat) {
-    if (it.kind == K_NOP) continue;
-    if (it.kind != K_MAC || it.tier != 0) return RTA_E_STATE;
-    if (it.group < 0 || it.group >= (int)groups.size()) return RTA_E_STATE;
-    const Group& gr = groups[it.group];
-    if (it.q < 0 || it.q >= c->Q) return RTA_E_STATE;
-    if (it.p0 < 2 || it.p1 < it.p0 || it.p1 > T.K) return RTA_E_STATE;
-    if (it.k0 < 0 || it.k0 % W != 0 || it.k0 + W > P) return RTA_E_STATE;
-    if (it.slot < gr.slot0 || it.slot >= gr.slot0 + gr.nslot) return RTA_E_STATE;
+  for (int t = 1; t < c->n_tiers; ++t)
+    for (int g = 0; g < ngroups; ++g) {
+      const int s0 = plan.tier_slot0[(size_t)t * ngroups + g], ns = plan.tier_nslot[(size_t)t * ngroups + g];
+      if (s0 < 0 || ns < 0 || s0 + ns > c->tier[t].nslots) return RTA_E_STATE;
+    }
+  for (int ph = 0; ph < n_phase; ++ph) {
+    for (const Item& it : plan.block[ph]) {
+      if (it.kind == K_NOP) continue;
+      if (it.kind != K_MAC || it.tier < 0 || it.tier >= c->n_tiers) return RTA_E_STATE;
+      if (it.group < 0 || it.group >= ngroups) return RTA_E_STATE;
+      const TierHost& T = c->tier[it.tier];
+      const int W = std::min(T.P, kThreads * C);
+      if (it.q < 0 || it.q >= c->Q) return RTA_E_STATE;
+      if (it.p0 < (it.tier == 0 ? 2 : 0) || it.p1 < it.p0 || it.p1 > T.K) return RTA_E_STATE;
+      if (it.k0 < 0 || it.k0 % W != 0 || it.k0 + W > T.P) return RTA_E_STATE;
+      if (it.tier == 0) {
+        const Group& gr = plan.groups[it.group];
+        if (it.slot < gr.slot0 || it.slot >= gr.slot0 + gr.nslot) return RTA_E_STATE;
+      } else {
+        const int s0 = plan.tier_slot0[(size_t)it.tier * ngroups + it.group];
+        const int ns = plan.tier_nslot[(size_t)it.tier * ngroups + it.group];
+        if (it.slot < s0 || it.slot >= s0 + ns) return RTA_E_STATE;
+        if (it.lag < 1 || it.lag > T.P / c->B) return RTA_E_STATE;
+      }
+    }
+    for (const Item& it : plan.tier[ph]) {
+      if (it.tier < 1 || it.tier >= c->n_tiers) return RTA_E_STATE;
+      if (it.kind == K_FFT && (it.q < 0 || it.q >= c->Q || it.lag != 0)) return RTA_E_STATE;
+      if (it.kind == K_FINAL && (it.group < 0 || it.group >= ngroups || it.lag < 1)) return RTA_E_STATE;
+      if (it.kind != K_FFT && it.kind != K_FINAL) return RTA_E_STATE;
+    }
   }
   return RTA_OK;
 }
@@ -386,6 +548,7 @@ KArgs make_args(const rta_ctx* c, const float* in, float* out, int64_t n) {
     d.logP = T.logP;
     d.K = T.K;
     d.nslots = std::max(1, T.nslots);
+    d.r = T.P / c->B;
   }
   a.items = c->items;
   a.phase_count = c->phase_count;
@@ -408,13 +571,22 @@ KArgs make_args(const rta_ctx* c, const float* in, float* out, int64_t n) {
   a.H01 = c->H01;
   a.head_count = c->head_count;
   a.done_flag = c->m_flag;
+  a.tier_items = c->tier_items;
+  a.tier_count = c->tier_count;
+  a.tier_slot0 = c->tier_slot0;
+  a.tier_nslot = c->tier_nslot;
+  a.max_tier_items = c->max_tier_items;
+  a.n_groups_total = c->n_groups;
   return a;
 }
 
-// One block: heads of block n and tails of block n + 1 in a single launch.
+// One block: heads of block n and tails of block n + 1 in a single launch,
+// then, in blocks with later-tier FFTs or finals, one k_tier launch.
 int launch_block(rta_ctx* c, const float* in, float* out, hipStream_t s) {
   const KArgs a = make_args(c, in, out, c->block);
-  const unsigned grid = (unsigned)(c->head_slots + c->n_items);
+  const unsigned grid = (unsigned)(c->head_slots + c->max_items);
+  const int phase = (int)(c->block % c->n_phase);
+  const int n_tier = c->tier_count_host.empty() ? 0 : c->tier_count_host[phase];
   hipEvent_t* e = nullptr;
   if (c->timing && c->events_used + 2 <= 2 * kMaxTimedBlocks) {
     while (c->events.size() < c->events_used + 2) {
@@ -428,6 +600,10 @@ int launch_block(rta_ctx* c, const float* in, float* out, hipStream_t s) {
   }
   hipLaunchKernelGGL(block_kernel(c->dtype, c->G), dim3(grid), dim3(kThreads), c->lds, s, a);
   HIP_TRY(c, hipGetLastError());
+  if (n_tier > 0) {
+    hipLaunchKernelGGL(tier_kernel(c->G), dim3(n_tier), dim3(kThreads), c->lds_tier, s, a);
+    HIP_TRY(c, hipGetLastError());
+  }
   if (e) HIP_TRY(c, hipEventRecord(e[1], s));
   c->block += 1;
   return RTA_OK;
@@ -439,7 +615,7 @@ int zero_state(rta_ctx* c) {
     HIP_TRY(c, hipMemsetAsync(T.X, 0, sizeof(float2) * (size_t)c->Q * T.K * T.P, c->stream));
     // before the first block the terms p >= 2 are all zero (zero history)
     HIP_TRY(c, hipMemsetAsync(T.partial, 0,
-                              sizeof(float2) * 2 * (size_t)std::max(1, T.nslots) * c->G * T.P,
+                              sizeof(float2) * (t == 0 ? 2 : 1) * (size_t)std::max(1, T.nslots) * c->G * T.P,
                               c->stream));
     if (T.oring)
       HIP_TRY(c, hipMemsetAsync(T.oring, 0, sizeof(float) * (size_t)c->L * c->ring_len, c->stream));
@@ -564,10 +740,11 @@ int create_impl(rta_ctx* c, const std::vector<int>& size, const std::vector<int>
     T.K = std::max(1, kmax);
     off += (int64_t)T.count * T.P;
     const size_t eb = spectra_elem_bytes(c->dtype);
+    const double per_block = (double)c->B / T.P;  // a tier's frame recurs every P/B blocks
     c->spectra_bytes += rows * T.P * (int64_t)eb;
-    c->h_bytes += (double)rows * T.P * eb;
-    c->cmacs += (double)rows * T.P;
-    c->x_bytes += (double)c->Q * kmax * T.P * 8.0;
+    c->h_bytes += (double)rows * T.P * eb * per_block;
+    c->cmacs += (double)rows * T.P * per_block;
+    c->x_bytes += (double)c->Q * kmax * T.P * 8.0 * per_block;
     if (t == 0) {
       double tail_rows = 0;
       for (int32_t kp : T.kp) tail_rows += std::max(0, kp - 2);
@@ -587,7 +764,12 @@ int create_impl(rta_ctx* c, const std::vector<int>& size, const std::vector<int>
   c->io_bytes = 4.0 * c->B * (c->Q + c->L);
   c->hist_len = std::max<int64_t>(2 * c->B, 2 * (int64_t)c->tier[c->n_tiers - 1].P);
   c->hist_len = int64_t(1) << ilog2(c->hist_len);
+  // later tiers store each frame's output up to o_t samples ahead of the
+  // block being emitted (their time-domain delay)
   c->ring_len = 1;
+  if (c->n_tiers > 1) c->ring_len = int64_t(1) << ilog2(c->tier[c->n_tiers - 1].offset + 2 * c->B);
+  for (int t = 1; t < c->n_tiers; ++t)
+    if ((st = dev_alloc(c, &c->tier[t].oring, (size_t)c->L * c->ring_len)) != RTA_OK) return st;
 
   // spectra, then the heads' dense copy of partitions 0 and 1
   if ((st = build_spectra(c, filters, lengths)) != RTA_OK) return st;
@@ -603,27 +785,50 @@ int create_impl(rta_ctx* c, const std::vector<int>& size, const std::vector<int>
   while (c->G > 1 && (int64_t)sizeof(float2) * head_lds(c->tier[0].P, c->G, 1).total + 64 > max_lds)
     c->G /= 2;
 
-  // tail work list
-  std::vector<Item> flat;
-  std::vector<Group> groups;
-  if ((st = build_plan(c, flat, groups)) != RTA_OK) return st;
-  c->n_phase = 1;
-  c->n_items = (int)flat.size();
-  c->max_items = std::max(1, c->n_items);
+  // work lists
+  Plan plan;
+  if ((st = build_plan(c, plan)) != RTA_OK) return st;
+  c->n_groups = (int)plan.groups.size();
   c->head_slots = (c->n_groups + kXcds - 1) / kXcds * kXcds;  // keeps tails' XCD residues
-  const int32_t pc = (int32_t)flat.size();
-  if ((st = dev_alloc(c, &c->items, (size_t)c->max_items)) != RTA_OK) return st;
-  if ((st = dev_alloc(c, &c->phase_count, 1)) != RTA_OK) return st;
-  if ((st = dev_alloc(c, &c->groups, groups.size())) != RTA_OK) return st;
+  size_t mb = 1, mt = 1;
+  for (int ph = 0; ph < c->n_phase; ++ph) {
+    mb = std::max(mb, plan.block[ph].size());
+    mt = std::max(mt, plan.tier[ph].size());
+  }
+  c->max_items = (int)mb;
+  c->max_tier_items = (int)mt;
+  c->n_items = (int)plan.block[0].size();
+  std::vector<Item> all_b((size_t)c->n_phase * mb, Item{}), all_t((size_t)c->n_phase * mt, Item{});
+  std::vector<int32_t> cnt_b(c->n_phase), cnt_t(c->n_phase);
+  for (auto& it : all_b) it.kind = K_NOP;
+  for (auto& it : all_t) it.kind = K_NOP;
+  for (int ph = 0; ph < c->n_phase; ++ph) {
+    std::copy(plan.block[ph].begin(), plan.block[ph].end(), all_b.begin() + (size_t)ph * mb);
+    std::copy(plan.tier[ph].begin(), plan.tier[ph].end(), all_t.begin() + (size_t)ph * mt);
+    cnt_b[ph] = (int32_t)plan.block[ph].size();
+    cnt_t[ph] = (int32_t)plan.tier[ph].size();
+  }
+  c->tier_count_host = cnt_t;
+  if ((st = dev_alloc(c, &c->items, all_b.size())) != RTA_OK) return st;
+  if ((st = dev_alloc(c, &c->phase_count, cnt_b.size())) != RTA_OK) return st;
+  if ((st = dev_alloc(c, &c->tier_items, all_t.size())) != RTA_OK) return st;
+  if ((st = dev_alloc(c, &c->tier_count, cnt_t.size())) != RTA_OK) return st;
+  if ((st = dev_alloc(c, &c->tier_slot0, plan.tier_slot0.size())) != RTA_OK) return st;
+  if ((st = dev_alloc(c, &c->tier_nslot, plan.tier_nslot.size())) != RTA_OK) return st;
+  if ((st = dev_alloc(c, &c->groups, plan.groups.size())) != RTA_OK) return st;
   if ((st = dev_alloc(c, &c->head_count, 1)) != RTA_OK) return st;
-  if (!flat.empty())
-    HIP_TRY(c, hipMemcpy(c->items, flat.data(), sizeof(Item) * flat.size(), hipMemcpyHostToDevice));
-  HIP_TRY(c, hipMemcpy(c->phase_count, &pc, sizeof(int32_t), hipMemcpyHostToDevice));
-  HIP_TRY(c, hipMemcpy(c->groups, groups.data(), sizeof(Group) * groups.size(), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(c->items, all_b.data(), sizeof(Item) * all_b.size(), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(c->phase_count, cnt_b.data(), sizeof(int32_t) * cnt_b.size(), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(c->tier_items, all_t.data(), sizeof(Item) * all_t.size(), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(c->tier_count, cnt_t.data(), sizeof(int32_t) * cnt_t.size(), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(c->tier_slot0, plan.tier_slot0.data(), sizeof(int32_t) * plan.tier_slot0.size(), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(c->tier_nslot, plan.tier_nslot.data(), sizeof(int32_t) * plan.tier_nslot.size(), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(c->groups, plan.groups.data(), sizeof(Group) * plan.groups.size(), hipMemcpyHostToDevice));
 
   for (int t = 0; t < c->n_tiers; ++t) {
     TierHost& T = c->tier[t];
-    if ((st = dev_alloc(c, &T.partial, 2 * (size_t)std::max(1, T.nslots) * c->G * T.P)) != RTA_OK)
+    const size_t bufs = t == 0 ? 2 : 1;  // the first tier's partials alternate by block parity
+    if ((st = dev_alloc(c, &T.partial, bufs * (size_t)std::max(1, T.nslots) * c->G * T.P)) != RTA_OK)
       return st;
   }
   if ((st = dev_alloc(c, &c->hist, (size_t)c->Q * c->hist_len)) != RTA_OK) return st;
@@ -655,6 +860,15 @@ int create_impl(rta_ctx* c, const std::vector<int>& size, const std::vector<int>
   if (c->lds > 65536)
     HIP_TRY(c, hipFuncSetAttribute(reinterpret_cast<const void*>(block_kernel(c->dtype, c->G)),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds));
+  if (c->n_tiers > 1) {
+    int pmax = 0;
+    for (int t = 1; t < c->n_tiers; ++t) pmax = std::max(pmax, c->tier[t].P);
+    c->lds_tier = sizeof(float2) * (size_t)tier_lds(pmax);
+    if ((int64_t)c->lds_tier + 64 > (int64_t)max_lds) return RTA_E_UNSUPPORTED;
+    if (c->lds_tier > 65536)
+      HIP_TRY(c, hipFuncSetAttribute(reinterpret_cast<const void*>(tier_kernel(c->G)),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_tier));
+  }
   return zero_state(c);
 }
 
@@ -768,7 +982,7 @@ int rta_query(rta_ctx* c, rta_info* info) {
   info->io_bytes_per_block = c->io_bytes;
   info->cmacs_per_block = c->cmacs;
   info->tail_bytes_per_block = c->tail_bytes;
-  info->grid = c->head_slots + c->n_items;
+  info->grid = c->head_slots + c->max_items;
   info->outputs_per_group = c->G;
   info->rows_per_item = c->rows_per_item;
   info->poisoned = c->poisoned ? 1 : 0;
