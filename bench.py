@@ -135,13 +135,19 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="main")
-    ap.add_argument("--spectra", default="fp32", choices=["fp32", "fp16", "bf16"])
+    ap.add_argument("--spectra", default=None, choices=["fp32", "fp16", "bf16"],
+                    help="spectra storage (default: the workload's)")
+    ap.add_argument("--scheme", default=None,
+                    help="partition scheme as size x count tiers, e.g. 128x15,1024x14,8192x0; "
+                         "'uniform' forces one tier (default: the workload's)")
     ap.add_argument("--latency-blocks", type=int, default=2000)
     ap.add_argument("--paced-blocks", type=int, default=1000,
                     help="host blocks issued one every B/fs (real-time pacing)")
     ap.add_argument("--cpu-channels", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mb", type=int, default=0)
+    ap.add_argument("--autotune", action="store_true",
+                    help="run the library's autotuner first and use its scheme and tiling")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -162,9 +168,13 @@ def main() -> int:
     from paper_2509_04390_amd import rta, workloads
 
     wl = workloads.config(args.workload)
-    if wl.scheme is not None:
-        print("bench.py: non-uniform schemes are not benchmarked yet", file=sys.stderr)
-        return 2
+    if args.spectra is None:
+        args.spectra = wl.dtype
+    scheme = wl.scheme
+    if args.scheme == "uniform":
+        scheme = None
+    elif args.scheme:
+        scheme = [tuple(int(v) for v in t.split("x")) for t in args.scheme.split(",")]
     B, Q, L, fs = wl.block, wl.n_in, wl.n_out, float(wl.fs)
     nblk = args.warmup + args.steps
     log(f"workload {wl.name}: Q={Q} L={L} taps={wl.lengths} B={B} spectra={args.spectra}")
@@ -172,8 +182,18 @@ def main() -> int:
     wl_steps = workloads.Workload(**{**wl.__dict__, "n_blocks": max(nblk, wl.n_blocks)})
     x = wl_steps.signal_array()
 
+    tuning, tuned = None, None
+    if args.autotune:
+        t0 = time.perf_counter()
+        tuning, chosen, us = rta.rta_autotune(fs, B, scheme, Q, L, filt, spectra=args.spectra,
+                                              blocks=64)
+        scheme = None if len(chosen) == 1 else chosen
+        tuned = {"scheme": chosen, "outputs_per_group": tuning.outputs_per_group,
+                 "tail_items": tuning.tail_items, "us_per_block": us,
+                 "seconds": time.perf_counter() - t0}
+        log(f"autotune: {tuned}")
     t0 = time.perf_counter()
-    cv = rta.Convolver(filt, B, fs=fs, spectra=args.spectra)
+    cv = rta.Convolver(filt, B, fs=fs, spectra=args.spectra, scheme=scheme, tuning=tuning)
     info = cv.info()
     log(f"created in {time.perf_counter() - t0:.2f} s: grid={info['grid']} "
         f"rows/item={info['rows_per_item']} G={info['outputs_per_group']} "
@@ -253,6 +273,10 @@ def main() -> int:
         cpu = cpu_baseline(wl, filt, x[:, :wl.n_blocks * B], args.cpu_channels)
 
     n_h = wl.max_len()
+    lens = [int(np.asarray(f).size) for row in filt for f in row]
+    taps_total = float(sum(lens))
+    tiers = ("uniform partitions" if scheme is None else
+             "tiers " + "/".join(f"{s_}x{c_ or 'rest'}" for s_, c_ in scheme))
     res = {
         "metric": METRIC,
         "value": value,
@@ -267,14 +291,15 @@ def main() -> int:
         "dtype": "f32" if args.spectra == "fp32" else f"f32 (spectra {args.spectra})",
         "data": "synthetic",
         "config": {
-            "workload": (f"{wl.name}: {Q} in -> {L} out, {n_h}-tap ({n_h / fs:.1f} s) "
-                         f"exp-decayed Gaussian filters, block {B} = partition {B}, "
-                         f"fs {int(fs)} Hz, {args.spectra} spectra, uniform partitions"),
+            "workload": (f"{wl.name}: {Q} in -> {L} out, up to {n_h}-tap ({n_h / fs:.1f} s) "
+                         f"exp-decayed Gaussian filters, block {B}, fs {int(fs)} Hz, "
+                         f"{args.spectra} spectra, {tiers}"),
             "block": B, "n_in": Q, "n_out": L, "taps": n_h, "spectra": args.spectra,
-            "partitions": info["tier_count"][0],
+            "tiers": [[int(a_), int(b_)] for a_, b_ in zip(info["tier_size"], info["tier_count"])],
+            "phases": info["n_phases"],
         },
         "rtf": (ms_per_step / 1e3) / audio_per_step,
-        "channel_filter_seconds_per_s": Q * L * (n_h / fs) * value,
+        "channel_filter_seconds_per_s": taps_total / fs * value,
         "deadline_us": deadline,
         "latency": paced,
         "latency_back_to_back": {"blocks": args.latency_blocks,
@@ -295,6 +320,7 @@ def main() -> int:
             "kernel_us_mean": kern_us,
         },
         "read_probe": probes,
+        "autotune": tuned,
         "cpu_baseline": cpu,
     }
     cv.close()

@@ -127,6 +127,50 @@ int rta_create(rta_ctx** out, double fs, int32_t block,
                const float* const* filters, const int64_t* lengths,
                int32_t spectra, uint32_t flags);
 
+/* Tiling of the kernels (performance only: every tiling gives the same
+ * output up to FP32 rounding order).  Zero in any field selects the default.
+ *   outputs_per_group  G in {1, 2, 4}: outputs sharing one input-spectrum
+ *                      load in the multiply-accumulate (default 2 when there
+ *                      are at least 16 outputs, else 1).
+ *   tail_items         target number of first-tier multiply-accumulate work
+ *                      items per block (default 1024).
+ *   tail_rows          partitions per first-tier item; overrides tail_items.
+ *   tier_rows          partitions per later-tier item (default 16).
+ * rta_autotune() also fills the scheme it selected (n_tiers, size, count). */
+typedef struct rta_tuning {
+    int32_t outputs_per_group;
+    int32_t tail_items;
+    int32_t tail_rows;
+    int32_t tier_rows;
+    int32_t n_tiers;
+    int32_t size[RTA_MAX_TIERS];
+    int32_t count[RTA_MAX_TIERS];
+} rta_tuning;
+
+/* rta_create() with an explicit tiling (NULL: defaults).  The scheme fields
+ * of `tuning` are ignored here; pass the scheme as `scheme`. */
+int rta_create_tuned(rta_ctx** out, double fs, int32_t block,
+                     const rta_scheme* scheme, int32_t n_in, int32_t n_out,
+                     const float* const* filters, const int64_t* lengths,
+                     int32_t spectra, uint32_t flags, const rta_tuning* tuning);
+
+/* Autotuner.  Same arguments as rta_create(), except that a NULL scheme
+ * means "choose one": the candidates are uniform partitioning and the
+ * non-uniform schemes with partition ratios 8 (B, 8B, 64B) and 4 (B, 4B,
+ * 16B, 64B), each tier starting exactly 2 P_t - B taps into the filter,
+ * limited to tiers the longest filter reaches and to sizes <= 8192.  For
+ * every candidate scheme and tiling (G in {1, 2, 4} x tail_items in {512,
+ * 1024, 2048}) a context is created, `blocks` blocks of zero input are run
+ * through rta_process_device() after 16 warm-up blocks, and the mean block
+ * time is measured with HIP events.  The fastest is written to *best and its
+ * mean block time in microseconds to *best_us.  Takes one to a few seconds
+ * per candidate, mostly building spectra; allocates and frees device memory
+ * on the current device. */
+int rta_autotune(double fs, int32_t block, const rta_scheme* scheme,
+                 int32_t n_in, int32_t n_out, const float* const* filters,
+                 const int64_t* lengths, int32_t spectra, uint32_t flags,
+                 int32_t blocks, rta_tuning* best, double* best_us);
+
 /* Process one block, host memory in and out, synchronously.
  *   in   [n_in][block] FP32 host array (row-major), read during the call.
  *   out  [n_out][block] FP32 host array, valid on return.

@@ -357,6 +357,66 @@ __device__ void reduce_slots(const DevTier& T, const Group& grp, int g, float2* 
   __syncthreads();
 }
 
+// Sum the first tier's partial slots of a whole output group, all its
+// outputs at once (elements e = g P + k are contiguous within a slot), and
+// add the p = 1 term sum_q H_{l,q,1} X_q(n-1), which needs no new spectrum.
+// With fewer than 256 elements, the threads form 256/E groups that each add
+// a contiguous run of slots, combined in group order (fixed for given E and
+// nslot, so results are reproducible).  Y: [G][P] in LDS; scratch: 256
+// float2.  Ends with a barrier.
+template <typename HT, int G>
+__device__ void head_reduce(const KArgs& A, const DevTier& T, const Group& grp, int64_t n,
+                            float2* Y, float2* scratch) {
+  const int P = T.P;
+  const int E = grp.nl * P;
+  const int64_t stride = (int64_t)G * P;
+  const float2* base = T.partial + (int64_t)grp.slot0 * stride;
+  const int tid = threadIdx.x;
+  const bool has_p1 = T.K >= 2;
+  const int slot1 = wrap_slot(n - 1, T.K);
+  const HT* H01 = reinterpret_cast<const HT*>(A.H01);
+  auto p1_term = [&](int e) {
+    float2 t = make_float2(0.f, 0.f);
+    if (!has_p1) return t;
+    const int g = e / P, k = e - g * P;
+    const int l = grp.l0 + g;
+    for (int q = 0; q < A.Q; ++q) {
+      const float2 h1 = HVec<HT>::load1(H01 + ((int64_t)(l * A.Q + q) * 2 + 1) * P + k);
+      const float2 x1 = T.X[((int64_t)q * T.K + slot1) * P + k];
+      t = cadd(t, (k == 0) ? make_float2(h1.x * x1.x, h1.y * x1.y) : cmul(h1, x1));
+    }
+    return t;
+  };
+  if (E >= kThreads) {
+    for (int e = tid; e < E; e += kThreads) {
+      float2 acc = p1_term(e);
+#pragma unroll 16
+      for (int sl = 0; sl < grp.nslot; ++sl) acc = cadd(acc, base[sl * stride + e]);
+      Y[e] = acc;
+    }
+    __syncthreads();
+    return;
+  }
+  const int ng = kThreads / E;
+  const int e = tid % E, tg = tid / E;
+  float2 acc = make_float2(0.f, 0.f);
+  if (tg < ng) {
+    const int per = (grp.nslot + ng - 1) / ng;
+    const int s0 = min(grp.nslot, tg * per), s1 = min(grp.nslot, s0 + per);
+    if (tg == 0) acc = p1_term(e);
+#pragma unroll 16
+    for (int sl = s0; sl < s1; ++sl) acc = cadd(acc, base[sl * stride + e]);
+  }
+  scratch[tid] = acc;
+  __syncthreads();
+  if (tid < E) {
+    float2 t = scratch[e];
+    for (int g2 = 1; g2 < ng; ++g2) t = cadd(t, scratch[g2 * E + e]);
+    Y[e] = t;
+  }
+  __syncthreads();
+}
+
 // LDS layout of a head workgroup, in float2 units (the host sizes the launch with the
 // same function): Y [G][P] | Xa [nbuf][P] | Xb [nbuf][P] | twiddles | 256.
 struct HeadLds {
@@ -389,18 +449,17 @@ __device__ void head_work(const KArgs& A, const Group& grp, float2* lds) {
   const float2* tw = stage_twiddles(T, lds + L.tw);
   const HT* H01 = reinterpret_cast<const HT*>(A.H01);
 
-  // 1. the terms p >= 2, summed by the previous launch's tail items
+  // 1. the terms p >= 2, summed by the previous launch's tail items, and the
+  //    term p = 1 (ring slot n-1)
   const DevTier Tcur = [&] {
     DevTier t = T;
     t.partial = T.partial + (n & 1) * (int64_t)T.nslots * G * P;
     return t;
   }();
-  for (int g = 0; g < grp.nl; ++g) reduce_slots<G>(Tcur, grp, g, Y + g * P, scratch);
+  head_reduce<HT, G>(A, Tcur, grp, n, Y, scratch);
 
-  // 2. the terms p = 0 (fresh spectrum) and p = 1 (ring slot n-1)
+  // 2. the term p = 0: window -> real FFT -> ring slot n mod K, times H_{l,q,0}
   const int slot0 = wrap_slot(n, T.K);
-  const int slot1 = wrap_slot(n - 1, T.K);
-  const bool has_p1 = T.K >= 2;
   for (int q0 = 0; q0 < A.Q; q0 += A.head_nq) {
     const int nb = min(A.head_nq, A.Q - q0);
     for (int e = tid; e < nb * P; e += kThreads) {
@@ -438,13 +497,7 @@ __device__ void head_work(const KArgs& A, const Group& grp, float2* lds) {
         const HT* h = H01 + ((int64_t)(l * A.Q + q) * 2) * P + k;
         const float2 h0 = HVec<HT>::load1(h);
         const float2 x0 = x[b * P + k];
-        float2 t0 = (k == 0) ? make_float2(h0.x * x0.x, h0.y * x0.y) : cmul(h0, x0);
-        if (has_p1) {
-          const float2 h1 = HVec<HT>::load1(h + P);
-          const float2 x1 = T.X[((int64_t)q * T.K + slot1) * P + k];
-          t0 = cadd(t0, (k == 0) ? make_float2(h1.x * x1.x, h1.y * x1.y) : cmul(h1, x1));
-        }
-        acc = cadd(acc, t0);
+        acc = cadd(acc, (k == 0) ? make_float2(h0.x * x0.x, h0.y * x0.y) : cmul(h0, x0));
       }
       Y[e] = acc;
     }
@@ -476,9 +529,10 @@ __device__ void head_work(const KArgs& A, const Group& grp, float2* lds) {
     A.out[(int64_t)l * A.B + i + 1] = y1;
   }
 
-  // 4. completion: every head makes its output visible system-wide, the
-  //    last one raises the flag (only the heads count, so the host does not
-  //    wait for the tail workgroups of this launch)
+  // 4. completion (rta_process only): every head makes its output visible
+  //    system-wide, the last one raises the flag (only the heads count, so
+  //    the host does not wait for the tail workgroups of this launch)
+  if (A.done_flag == nullptr) return;
   __threadfence_system();
   __syncthreads();
   if (tid == 0) {

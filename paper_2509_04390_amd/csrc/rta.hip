@@ -59,12 +59,6 @@ int ilog2(int64_t v) {
 }
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
-int env_int(const char* name, int dflt) {
-  const char* s = std::getenv(name);
-  if (s == nullptr || *s == 0) return dflt;
-  return std::atoi(s);
-}
-
 }  // namespace
 
 struct rta_ctx {
@@ -76,6 +70,7 @@ struct rta_ctx {
   int n_tiers = 0;
   TierHost tier[kMaxTiers];
   int G = 1, rows_per_item = 0, n_phase = 1, max_items = 0, n_items = 0;
+  int tail_items = 1024, tier_rows = 16;
   int n_groups = 0, head_slots = 0, head_nq = 1;
   int64_t hist_len = 0, ring_len = 0;
   size_t lds = 0;              // k_block dynamic LDS
@@ -369,7 +364,7 @@ int build_plan(rta_ctx* c, Plan& plan) {
       for (int q = 0; q < c->Q; ++q) total_rows += std::max(0, group_rows(T, gr, q) - 2);
     int R = c->rows_per_item;
     if (R <= 0) {
-      const int64_t target_items = env_int("RTA_TARGET_ITEMS", 1024);
+      const int64_t target_items = std::max(1, c->tail_items);
       R = (int)std::max<int64_t>(8, (total_rows * nslice + target_items - 1) / target_items);
     }
     c->rows_per_item = R;
@@ -414,7 +409,7 @@ int build_plan(rta_ctx* c, Plan& plan) {
     const int r = P / c->B;
     const int nmac = tier_nmac(c, t);
     if (nmac < 1) return RTA_E_STATE;
-    const int R = std::max(1, env_int("RTA_TIER_ROWS", 16));
+    const int R = std::max(1, c->tier_rows);
     struct Chunk { int g, q, p0, p1, slot; };
     std::vector<Chunk> chunks;
     int slot = 0;
@@ -570,7 +565,7 @@ KArgs make_args(const rta_ctx* c, const float* in, float* out, int64_t n) {
   a.n = n;
   a.H01 = c->H01;
   a.head_count = c->head_count;
-  a.done_flag = c->m_flag;
+  a.done_flag = nullptr;  // set by rta_process, which polls it
   a.tier_items = c->tier_items;
   a.tier_count = c->tier_count;
   a.tier_slot0 = c->tier_slot0;
@@ -582,8 +577,10 @@ KArgs make_args(const rta_ctx* c, const float* in, float* out, int64_t n) {
 
 // One block: heads of block n and tails of block n + 1 in a single launch,
 // then, in blocks with later-tier FFTs or finals, one k_tier launch.
-int launch_block(rta_ctx* c, const float* in, float* out, hipStream_t s) {
-  const KArgs a = make_args(c, in, out, c->block);
+// `flag`: raise the host-visible completion flag (rta_process).
+int launch_block(rta_ctx* c, const float* in, float* out, hipStream_t s, bool flag = false) {
+  KArgs a = make_args(c, in, out, c->block);
+  if (flag) a.done_flag = c->m_flag;
   const unsigned grid = (unsigned)(c->head_slots + c->max_items);
   const int phase = (int)(c->block % c->n_phase);
   const int n_tier = c->tier_count_host.empty() ? 0 : c->tier_count_host[phase];
@@ -886,16 +883,83 @@ void free_all(rta_ctx* c) {
 
 }  // namespace
 
+namespace {
+
+// Candidate schemes of the autotuner: uniform, and for partition ratios 8
+// and 4 the tiers B, rB, r^2 B, ... (<= 8192) with tier t >= 1 starting at
+// 2 P_t - B, kept while the longest filter reaches them.
+std::vector<std::vector<std::pair<int, int>>> scheme_candidates(int B, int64_t max_len) {
+  std::vector<std::vector<std::pair<int, int>>> out;
+  out.push_back({{B, 0}});
+  for (int ratio : {8, 4}) {
+    std::vector<std::pair<int, int>> sch;
+    int64_t o = 0;
+    int64_t P = B;
+    while (true) {
+      const int64_t Pn = P * ratio;
+      const int64_t on = 2 * Pn - B;  // start of the next tier
+      if (Pn > 8192 || max_len <= on) break;
+      sch.push_back({(int)P, (int)((on - o) / P)});
+      o = on;
+      P = Pn;
+    }
+    if (sch.empty()) continue;
+    sch.push_back({(int)P, 0});
+    if (std::find(out.begin(), out.end(), sch) == out.end()) out.push_back(sch);
+  }
+  return out;
+}
+
+// Mean block time (us) of one context over `blocks` device-path blocks.
+int time_blocks(rta_ctx* c, int blocks, double* us) {
+  float* din = nullptr;
+  float* dout = nullptr;
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int st = RTA_OK;
+  float ms = 0.f;
+  if (hipMalloc(&din, sizeof(float) * (size_t)c->Q * c->B) != hipSuccess ||
+      hipMalloc(&dout, sizeof(float) * (size_t)c->L * c->B) != hipSuccess ||
+      hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
+      hipMemset(din, 0, sizeof(float) * (size_t)c->Q * c->B) != hipSuccess) {
+    st = RTA_E_DEVICE;
+  }
+  for (int i = 0; st == RTA_OK && i < 16; ++i) st = rta_process_device(c, din, dout, s);
+  if (st == RTA_OK && hipEventRecord(e0, s) != hipSuccess) st = RTA_E_DEVICE;
+  for (int i = 0; st == RTA_OK && i < blocks; ++i) st = rta_process_device(c, din, dout, s);
+  if (st == RTA_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                       hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+    st = RTA_E_DEVICE;
+  if (st == RTA_OK) *us = 1e3 * ms / blocks;
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (s) (void)hipStreamDestroy(s);
+  if (din) (void)hipFree(din);
+  if (dout) (void)hipFree(dout);
+  (void)hipGetLastError();
+  return st;
+}
+
+}  // namespace
+
 extern "C" {
 
-int rta_create(rta_ctx** out, double fs, int32_t block, const rta_scheme* scheme, int32_t n_in,
-               int32_t n_out, const float* const* filters, const int64_t* lengths,
-               int32_t spectra, uint32_t flags) {
+int rta_create_tuned(rta_ctx** out, double fs, int32_t block, const rta_scheme* scheme,
+                     int32_t n_in, int32_t n_out, const float* const* filters,
+                     const int64_t* lengths, int32_t spectra, uint32_t flags,
+                     const rta_tuning* tuning) {
   if (out == nullptr) return RTA_E_ARG;
   *out = nullptr;
   std::vector<int> size, count;
   int st = validate(fs, block, scheme, n_in, n_out, filters, lengths, spectra, flags, size, count);
   if (st != RTA_OK) return st;
+  if (tuning != nullptr) {
+    const int g = tuning->outputs_per_group;
+    if ((g != 0 && g != 1 && g != 2 && g != 4) || tuning->tail_items < 0 || tuning->tail_rows < 0 ||
+        tuning->tier_rows < 0)
+      return RTA_E_ARG;
+  }
   rta_ctx* c = new (std::nothrow) rta_ctx();
   if (c == nullptr) return RTA_E_NOMEM;
   c->fs = fs;
@@ -905,10 +969,14 @@ int rta_create(rta_ctx** out, double fs, int32_t block, const rta_scheme* scheme
   c->dtype = spectra;
   c->flags = flags;
   // tiling defaults measured on the 1 -> 32 x 480,000-tap workload: two
-  // outputs per workgroup and about 1,024 tail items (env overrides for tuning)
-  c->G = env_int("RTA_G", n_out >= 16 ? 2 : 1);
-  if (c->G != 1 && c->G != 2 && c->G != 4) c->G = 1;
-  c->rows_per_item = env_int("RTA_ROWS", 0);
+  // outputs per workgroup and about 1,024 first-tier items
+  c->G = n_out >= 16 ? 2 : 1;
+  if (tuning != nullptr) {
+    if (tuning->outputs_per_group) c->G = tuning->outputs_per_group;
+    if (tuning->tail_items) c->tail_items = tuning->tail_items;
+    if (tuning->tail_rows) c->rows_per_item = tuning->tail_rows;
+    if (tuning->tier_rows) c->tier_rows = tuning->tier_rows;
+  }
   st = create_impl(c, size, count, filters, lengths);
   if (st != RTA_OK) {
     free_all(c);
@@ -919,12 +987,19 @@ int rta_create(rta_ctx** out, double fs, int32_t block, const rta_scheme* scheme
   return RTA_OK;
 }
 
+int rta_create(rta_ctx** out, double fs, int32_t block, const rta_scheme* scheme, int32_t n_in,
+               int32_t n_out, const float* const* filters, const int64_t* lengths,
+               int32_t spectra, uint32_t flags) {
+  return rta_create_tuned(out, fs, block, scheme, n_in, n_out, filters, lengths, spectra, flags,
+                          nullptr);
+}
+
 int rta_process(rta_ctx* c, const float* in, float* out) {
   if (c == nullptr || in == nullptr || out == nullptr) return RTA_E_ARG;
   if (c->poisoned) return RTA_E_DEVICE;
   std::memcpy(c->h_in, in, sizeof(float) * (size_t)c->Q * c->B);
   const int64_t want = c->block + 1;
-  int st = launch_block(c, c->m_in, c->m_out, c->stream);
+  int st = launch_block(c, c->m_in, c->m_out, c->stream, true);
   if (st != RTA_OK) return st;
   // spin until the last head has raised the flag; the tail workgroups of the
   // same launch keep running.  Every few thousand polls the stream is asked
@@ -1017,6 +1092,77 @@ int rta_probe_read(const void* d_buf, int64_t bytes, int32_t grid, float* d_sink
   hipLaunchKernelGGL(k_read_probe, dim3(grid), dim3(kThreads), 0, static_cast<hipStream_t>(stream),
                      static_cast<const f32x4*>(d_buf), bytes / 16, d_sink);
   return hipGetLastError() == hipSuccess ? RTA_OK : RTA_E_DEVICE;
+}
+
+int rta_autotune(double fs, int32_t block, const rta_scheme* scheme, int32_t n_in, int32_t n_out,
+                 const float* const* filters, const int64_t* lengths, int32_t spectra,
+                 uint32_t flags, int32_t blocks, rta_tuning* best, double* best_us) {
+  if (best == nullptr || best_us == nullptr || blocks < 1) return RTA_E_ARG;
+  std::vector<int> size, count;
+  int st = validate(fs, block, scheme, n_in, n_out, filters, lengths, spectra, flags, size, count);
+  if (st != RTA_OK) return st;
+  int64_t max_len = 0;
+  for (int64_t i = 0; i < (int64_t)n_in * n_out; ++i) max_len = std::max(max_len, lengths[i]);
+  std::vector<std::vector<std::pair<int, int>>> schemes;
+  if (scheme != nullptr) {
+    std::vector<std::pair<int, int>> sch;
+    for (size_t t = 0; t < size.size(); ++t) sch.push_back({size[t], count[t]});
+    schemes.push_back(sch);
+  } else {
+    schemes = scheme_candidates(block, max_len);
+  }
+  auto trial = [&](const std::vector<std::pair<int, int>>& sch, const rta_tuning& tu, double* us) {
+    std::vector<int32_t> sz, ct;
+    for (auto& p : sch) {
+      sz.push_back(p.first);
+      ct.push_back(p.second);
+    }
+    rta_scheme rs{(int32_t)sch.size(), sz.data(), ct.data()};
+    rta_ctx* c = nullptr;
+    int s2 = rta_create_tuned(&c, fs, block, &rs, n_in, n_out, filters, lengths, spectra, flags, &tu);
+    if (s2 != RTA_OK) return s2;
+    s2 = time_blocks(c, blocks, us);
+    rta_destroy(c);
+    return s2;
+  };
+  // stage 1: the scheme, with default tiles; stage 2: the tiles, for that scheme
+  double best_t = 1e300;
+  size_t best_s = 0;
+  for (size_t i = 0; i < schemes.size(); ++i) {
+    double us = 0;
+    const rta_tuning tu{};
+    const int s2 = trial(schemes[i], tu, &us);
+    if (s2 == RTA_E_DEVICE) return s2;
+    if (s2 == RTA_OK && us < best_t) {
+      best_t = us;
+      best_s = i;
+    }
+  }
+  if (best_t == 1e300) return RTA_E_UNSUPPORTED;
+  rta_tuning bt{};
+  for (int g : {1, 2, 4}) {
+    if (g > n_out) continue;
+    for (int items : {512, 1024, 2048}) {
+      rta_tuning tu{};
+      tu.outputs_per_group = g;
+      tu.tail_items = items;
+      double us = 0;
+      const int s2 = trial(schemes[best_s], tu, &us);
+      if (s2 == RTA_E_DEVICE) return s2;
+      if (s2 == RTA_OK && us < best_t) {
+        best_t = us;
+        bt = tu;
+      }
+    }
+  }
+  bt.n_tiers = (int32_t)schemes[best_s].size();
+  for (int t = 0; t < bt.n_tiers; ++t) {
+    bt.size[t] = schemes[best_s][t].first;
+    bt.count[t] = schemes[best_s][t].second;
+  }
+  *best = bt;
+  *best_us = best_t;
+  return RTA_OK;
 }
 
 int rta_destroy(rta_ctx* c) {

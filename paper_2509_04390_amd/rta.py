@@ -12,6 +12,15 @@ from typing import List, Optional, Sequence
 
 import numpy as np
 
+# PyTorch-ROCm ships its own HIP runtime.  If librta.so were loaded first,
+# a later `import torch` would bring a second HIP runtime into the process and
+# the library's device calls would fail; importing torch first (when it is
+# installed) makes librta.so bind to torch's runtime, so the process has one.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
+
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librta.so")
 if not os.path.exists(_LIB_PATH):
     raise ImportError(f"{_LIB_PATH} is missing: build it first "
@@ -34,7 +43,7 @@ RTA_MAX_TIERS = 8
 
 EXPORTED = ("rta_create", "rta_process", "rta_process_device", "rta_reset",
             "rta_query", "rta_timing_enable", "rta_timing_read", "rta_probe_read",
-            "rta_destroy", "rta_strerror")
+            "rta_destroy", "rta_strerror", "rta_create_tuned", "rta_autotune")
 
 
 class rta_scheme(ctypes.Structure):
@@ -66,11 +75,27 @@ class rta_info(ctypes.Structure):
                 ("poisoned", ctypes.c_int32)]
 
 
+class rta_tuning(ctypes.Structure):
+    _fields_ = [("outputs_per_group", ctypes.c_int32),
+                ("tail_items", ctypes.c_int32),
+                ("tail_rows", ctypes.c_int32),
+                ("tier_rows", ctypes.c_int32),
+                ("n_tiers", ctypes.c_int32),
+                ("size", ctypes.c_int32 * RTA_MAX_TIERS),
+                ("count", ctypes.c_int32 * RTA_MAX_TIERS)]
+
+
 _fp = ctypes.POINTER(ctypes.c_float)
 _lib.rta_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_double, ctypes.c_int32,
                             ctypes.POINTER(rta_scheme), ctypes.c_int32, ctypes.c_int32,
                             ctypes.POINTER(_fp), ctypes.POINTER(ctypes.c_int64),
                             ctypes.c_int32, ctypes.c_uint32]
+_lib.rta_create_tuned.argtypes = _lib.rta_create.argtypes + [ctypes.POINTER(rta_tuning)]
+_lib.rta_autotune.argtypes = [ctypes.c_double, ctypes.c_int32, ctypes.POINTER(rta_scheme),
+                              ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_fp),
+                              ctypes.POINTER(ctypes.c_int64), ctypes.c_int32, ctypes.c_uint32,
+                              ctypes.c_int32, ctypes.POINTER(rta_tuning),
+                              ctypes.POINTER(ctypes.c_double)]
 _lib.rta_process.argtypes = [ctypes.c_void_p, _fp, _fp]
 _lib.rta_process_device.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_void_p]
@@ -85,7 +110,8 @@ _lib.rta_timing_read.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)
 _lib.rta_strerror.argtypes = [ctypes.c_int]
 _lib.rta_strerror.restype = ctypes.c_char_p
 for _f in ("rta_create", "rta_process", "rta_process_device", "rta_reset", "rta_query",
-           "rta_timing_enable", "rta_timing_read", "rta_probe_read", "rta_destroy"):
+           "rta_timing_enable", "rta_timing_read", "rta_probe_read", "rta_destroy",
+           "rta_create_tuned", "rta_autotune"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -117,12 +143,7 @@ def rta_strerror(status: int) -> str:
     return _lib.rta_strerror(int(status)).decode()
 
 
-def rta_create(fs: float, block: int, scheme: Optional[Sequence[Sequence[int]]],
-               n_in: int, n_out: int, filters, lengths=None, spectra="fp32",
-               flags: int = 0) -> ctypes.c_void_p:
-    """filters: Q x L nested list of 1-D float32 arrays (None/empty = no path),
-    or a flat length-Q*L list in [in][out] order.  scheme: None (UPOLS) or a
-    sequence of (size, count) tiers.  Returns the opaque context handle."""
+def _marshal(filters, n_in, n_out, lengths, scheme):
     flat = _flatten(filters, n_in, n_out)
     keep = [np.ascontiguousarray(f, dtype=np.float32) if f is not None and len(f) else None
             for f in flat]
@@ -139,6 +160,38 @@ def rta_create(fs: float, block: int, scheme: Optional[Sequence[Sequence[int]]],
         sizes = (ctypes.c_int32 * len(scheme))(*[int(s) for s, _ in scheme])
         counts = (ctypes.c_int32 * len(scheme))(*[int(c) for _, c in scheme])
         sch = rta_scheme(len(scheme), sizes, counts)
+        sch._keep = (sizes, counts)
+    return keep, ptrs, lens, sch
+
+
+def make_tuning(outputs_per_group=0, tail_items=0, tail_rows=0, tier_rows=0) -> rta_tuning:
+    t = rta_tuning()
+    t.outputs_per_group, t.tail_items = outputs_per_group, tail_items
+    t.tail_rows, t.tier_rows = tail_rows, tier_rows
+    return t
+
+
+def rta_create_tuned(fs: float, block: int, scheme, n_in: int, n_out: int, filters,
+                     lengths=None, spectra="fp32", flags: int = 0, tuning=None):
+    """filters: Q x L nested list of 1-D float32 arrays (None/empty = no path),
+    or a flat length-Q*L list in [in][out] order.  scheme: None (UPOLS) or a
+    sequence of (size, count) tiers.  tuning: rta_tuning or None.  Returns the
+    opaque context handle."""
+    keep, ptrs, lens, sch = _marshal(filters, n_in, n_out, lengths, scheme)
+    dtype = DTYPES[spectra] if isinstance(spectra, str) else int(spectra)
+    ctx = ctypes.c_void_p()
+    st = _lib.rta_create_tuned(ctypes.byref(ctx), float(fs), int(block),
+                               ctypes.byref(sch) if sch is not None else None,
+                               int(n_in), int(n_out), ptrs, lens, dtype, int(flags),
+                               ctypes.byref(tuning) if tuning is not None else None)
+    _check(st, "rta_create_tuned")
+    return ctx
+
+
+def rta_create(fs: float, block: int, scheme, n_in: int, n_out: int, filters,
+               lengths=None, spectra="fp32", flags: int = 0):
+    """As rta_create_tuned with default tiling."""
+    keep, ptrs, lens, sch = _marshal(filters, n_in, n_out, lengths, scheme)
     dtype = DTYPES[spectra] if isinstance(spectra, str) else int(spectra)
     ctx = ctypes.c_void_p()
     st = _lib.rta_create(ctypes.byref(ctx), float(fs), int(block),
@@ -146,6 +199,21 @@ def rta_create(fs: float, block: int, scheme: Optional[Sequence[Sequence[int]]],
                          int(n_in), int(n_out), ptrs, lens, dtype, int(flags))
     _check(st, "rta_create")
     return ctx
+
+
+def rta_autotune(fs: float, block: int, scheme, n_in: int, n_out: int, filters,
+                 lengths=None, spectra="fp32", flags: int = 0, blocks: int = 64):
+    """Returns (tuning, scheme [(size, count), ...], mean block time in us)."""
+    keep, ptrs, lens, sch = _marshal(filters, n_in, n_out, lengths, scheme)
+    dtype = DTYPES[spectra] if isinstance(spectra, str) else int(spectra)
+    best = rta_tuning()
+    us = ctypes.c_double()
+    st = _lib.rta_autotune(float(fs), int(block), ctypes.byref(sch) if sch is not None else None,
+                           int(n_in), int(n_out), ptrs, lens, dtype, int(flags), int(blocks),
+                           ctypes.byref(best), ctypes.byref(us))
+    _check(st, "rta_autotune")
+    chosen = [(best.size[t], best.count[t]) for t in range(best.n_tiers)]
+    return best, chosen, us.value
 
 
 def rta_process(ctx, inp: np.ndarray, out: np.ndarray) -> None:
@@ -219,12 +287,13 @@ class Convolver:
     tensors on the current stream) and ``run`` (whole host signal)."""
 
     def __init__(self, filters, block: int, fs: float = 48000.0, scheme=None,
-                 spectra="fp32", flags: int = 0):
+                 spectra="fp32", flags: int = 0, tuning=None):
         self.n_in = len(filters)
         self.n_out = len(filters[0])
         self.block = block
-        self.ctx = rta_create(fs, block, scheme, self.n_in, self.n_out, filters,
-                              spectra=spectra, flags=flags)
+        self.ctx = None
+        self.ctx = rta_create_tuned(fs, block, scheme, self.n_in, self.n_out, filters,
+                                    spectra=spectra, flags=flags, tuning=tuning)
 
     def close(self):
         if self.ctx is not None:

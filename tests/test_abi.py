@@ -55,6 +55,8 @@ def test_destroy_null_and_null_handles_are_rejected(rta):
     assert lib.rta_timing_enable(None, 1) == rta.RTA_E_ARG
     assert lib.rta_timing_read(None, None, None) == rta.RTA_E_ARG
     assert lib.rta_create(None, 48000.0, 128, None, 1, 1, None, None, 0, 0) == rta.RTA_E_ARG
+    assert lib.rta_create_tuned(None, 48000.0, 128, None, 1, 1, None, None, 0, 0, None) == rta.RTA_E_ARG
+    assert lib.rta_autotune(48000.0, 128, None, 1, 1, None, None, 0, 0, 8, None, None) == rta.RTA_E_ARG
 
 
 def _create_status(rta, fs=48000.0, block=128, scheme=None, n_in=1, n_out=1,
@@ -98,3 +100,15 @@ def test_table1_buffer_latency_matches_block_over_fs(rta):
     assert len(rows) == 9
     for block, ms in rows:
         assert round(rta.deadline_us(int(block), 48000.0) / 1000.0, 2) == float(ms)
+
+
+def test_invalid_tuning_is_rejected_before_any_device_call(rta):
+    taps = np.ones(256, np.float32)
+    fp = ctypes.POINTER(ctypes.c_float)
+    ptrs = (fp * 1)(taps.ctypes.data_as(fp))
+    lengths = (ctypes.c_int64 * 1)(256)
+    for bad in (dict(outputs_per_group=3), dict(tail_items=-1), dict(tier_rows=-5)):
+        ctx = ctypes.c_void_p()
+        st = rta._lib.rta_create_tuned(ctypes.byref(ctx), 48000.0, 128, None, 1, 1, ptrs, lengths,
+                                       0, 0, ctypes.byref(rta.make_tuning(**bad)))
+        assert st == rta.RTA_E_ARG and not ctx.value

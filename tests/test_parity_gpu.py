@@ -6,7 +6,6 @@ compared sample by sample over the whole output including the filter tail;
 the full-size 1 -> 32 x 480,000-tap case is compared at sampled outputs that
 the oracle evaluates one by one.
 """
-import os
 import sys
 
 import numpy as np
@@ -31,24 +30,6 @@ def rta():
 def say(msg):
     print(msg, flush=True)
     sys.stdout.flush()
-
-
-class env:
-    """Temporarily set tuning environment variables read at rta_create."""
-
-    def __init__(self, **kw):
-        self.kw = {k: str(v) for k, v in kw.items()}
-
-    def __enter__(self):
-        self.old = {k: os.environ.get(k) for k in self.kw}
-        os.environ.update(self.kw)
-
-    def __exit__(self, *a):
-        for k, v in self.old.items():
-            if v is None:
-                os.environ.pop(k, None)
-            else:
-                os.environ[k] = v
 
 
 def make_filters(seed, lens, rt60=0.3):
@@ -102,9 +83,9 @@ def test_upols_fp32_matches_oracle_full_length(rta, case, G):
     maxlen = max(max(r) for r in lens)
     x = padded_signal(case + 50, Q, nb, B, maxlen)
     say(f"case {case}: B={B} Q={Q} L={L} lens={lens} G={G} samples={x.shape[1]}")
-    with env(RTA_G=G, RTA_ROWS=3):
-        with rta.Convolver(filt, B) as cv:
-            y = cv.run(x)
+    # three partitions per work item: many items and partial slots even here
+    with rta.Convolver(filt, B, tuning=rta.make_tuning(outputs_per_group=G, tail_rows=3)) as cv:
+        y = cv.run(x)
     ref = oracle.direct(x, filt, 0, x.shape[1])
     check_db(y, ref, FP32_DB, f"B={B} G={G}")
 
@@ -113,16 +94,15 @@ def test_device_path_equals_host_path_and_reruns_are_bitwise(rta):
     B, lens, nb = CASES[5]
     filt = make_filters(77, lens)
     x = padded_signal(78, len(lens), nb, B, 5000)
-    with env(RTA_ROWS=4):
-        with rta.Convolver(filt, B) as cv:
-            say("host path")
-            y1 = cv.run(x)
-            cv.reset()
-            say("device path")
-            y2 = cv.run_device(x)
-            cv.reset()
-            y3 = cv.run(x)
-            assert cv.info()["blocks_done"] == x.shape[1] // B
+    with rta.Convolver(filt, B, tuning=rta.make_tuning(tail_rows=4)) as cv:
+        say("host path")
+        y1 = cv.run(x)
+        cv.reset()
+        say("device path")
+        y2 = cv.run_device(x)
+        cv.reset()
+        y3 = cv.run(x)
+        assert cv.info()["blocks_done"] == x.shape[1] // B
     assert np.array_equal(y1, y2)
     assert np.array_equal(y1, y3)
 
@@ -221,3 +201,18 @@ def test_main_config_full_size_sampled(rta):
     idx = np.unique(np.r_[0, 1, 127, 128, n - 1, n - 128, rng.integers(0, n, 200)])
     ref = oracle.direct_at(x, filt, idx)
     check_db(y[:, idx], ref, FP32_DB, "main/direct")
+
+
+def test_autotune_returns_a_tuning_that_matches_the_oracle(rta):
+    B = 64
+    lens = [[30000, 9000, 0], [12000, 30000, 500]]
+    filt = make_filters(21, lens)
+    tuning, scheme, us = rta.rta_autotune(48000.0, B, None, 2, 3, filt, blocks=16)
+    say(f"autotune: scheme {scheme}, G={tuning.outputs_per_group}, "
+        f"items={tuning.tail_items}, {us:.1f} us/block")
+    assert scheme[0] == (B, scheme[0][1]) and us > 0
+    x = padded_signal(22, 2, 40, B, 30000)
+    with rta.Convolver(filt, B, scheme=scheme, tuning=tuning) as cv:
+        y = cv.run(x)
+    ref = oracle.fftols(x, filt, x.shape[1])
+    check_db(y, ref, FP32_DB, "autotuned")
