@@ -12,7 +12,9 @@ for each (q,l) pair), in IEEE double, in two independent forms:
   0-based causal indices, summed over inputs as in Eq. 2);
 * ``fftols``: one FFT overlap-save partition per filter (Eq. 5 applied to
   successive input segments; only wrap-free samples kept, Sec. IV step 3),
-  with the oracle's own radix-2 FFT (``fft``).
+  with the oracle's own radix-2 FFT (``fft``);
+* ``feedback_loop``: the auralization step with feedback cancellation
+  (Sec. III-A Eq. 3, Sec. V), block-recursive, direct sums.
 
 The C code lives in ``rta_oracle.c`` and is built with gcc by
 ``build_library()``.  Inputs: ``x`` is ``[Q][n_x]`` (any float array; it is
@@ -60,10 +62,12 @@ def _load():
     lib.orc_direct_at.argtypes = [ctypes.c_int, ctypes.c_int, dp, i64, dp, ip,
                                   ip, i64, dp]
     lib.orc_fft.argtypes = [dp, dp, i64, ctypes.c_int]
+    lib.orc_feedback_loop.argtypes = [ctypes.c_int, ctypes.c_int, dp, i64, i64, dp, ip, dp, ip,
+                                      dp, dp, dp]
     lib.orc_fftols.argtypes = [ctypes.c_int, ctypes.c_int, dp, i64, dp, ip,
                                i64, dp]
     for f in (lib.orc_direct_range, lib.orc_direct_at, lib.orc_fft,
-              lib.orc_fftols):
+              lib.orc_fftols, lib.orc_feedback_loop):
         f.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -130,6 +134,27 @@ def fftols(x, filters, n_y: int) -> np.ndarray:
     _check(_load().orc_fftols(Q, L, _dp(x), x.shape[1], _dp(h), _ip(off), n_y,
                               _dp(y)), "fftols")
     return y
+
+
+def feedback_loop(m, synth, feedback, block: int):
+    """Closed feedback-cancellation loop (Sec. III-A Eq. 3, Sec. V), block by
+    block: mt = m - c delayed by one block, l = H^T * mt, c = F-hat * l.
+
+    m: [P][N] microphone signals; synth: P x L nested filters h_pl (Eq. 1's
+    H); feedback: P x L nested filters f_pl (Eq. 3's F-hat, loudspeaker l to
+    microphone p).  Returns (l [L][N], c [P][N], mt [P][N])."""
+    m, h, hoff, P, L = _pack(m, synth)
+    _, f, foff, P2, L2 = _pack(m, feedback)
+    if (P2, L2) != (P, L):
+        raise ValueError("synthesis and feedback matrices must both be P x L")
+    N = m.shape[1]
+    l_out = np.zeros((L, N))
+    c_out = np.zeros((P, N))
+    mt = np.zeros((P, N))
+    _check(_load().orc_feedback_loop(P, L, _dp(m), N, int(block), _dp(h), _ip(hoff), _dp(f),
+                                     _ip(foff), _dp(l_out), _dp(c_out), _dp(mt)),
+           "feedback_loop")
+    return l_out, c_out, mt
 
 
 def fft(z, inverse: bool = False) -> np.ndarray:

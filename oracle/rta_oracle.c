@@ -27,6 +27,17 @@
  * IEEE double; the build uses -ffp-contract=off so no FMA contraction
  * changes rounding between compilers.
  *
+ * Feedback-cancellation loop (Sec. III-A Eq. 3 and Sec. V, the paper's
+ * auralization step): with P microphone signals m_p, synthesis filters
+ * h_pl (P x L, the H of Eq. 1) and estimated feedback paths f_pl (P x L,
+ * the F-hat of Eq. 3, path from loudspeaker l to microphone p), block by
+ * block of B samples
+ *     mt_p[t] = m_p[t] - c_p[t - B]          (c_p[t] = 0 for t < 0)
+ *     l_l[t]  = sum_p sum_j h_pl[j] mt_p[t - j]
+ *     c_p[t]  = sum_l sum_j f_pl[j] l_l[t - j]
+ * i.e. the feedback estimate of one block is subtracted from the next block
+ * of microphone samples.  Every sum is the direct form above.
+ *
  * Return codes: 0 on success, -1 on an invalid argument, -2 if memory for
  * the FFT work buffers cannot be allocated.
  */
@@ -236,4 +247,54 @@ int orc_fftols(int Q, int L, const double* x, int64_t nx, const double* h,
     free(wre);
     free(wim);
     return status;
+}
+
+/* Closed feedback-cancellation loop (see the file header).  m is [P][N];
+ * h and f are P x L pair arrays with offsets hoff/foff (pair (p,l) at
+ * index p*L+l); l_out is [L][N], c_out is [P][N], mt_out ([P][N]) may be
+ * NULL.  The blocks are processed in order; within a block every output
+ * sample only uses samples of the same or earlier blocks. */
+int orc_feedback_loop(int P, int L, const double* m, int64_t N, int64_t B,
+                      const double* h, const int64_t* hoff, const double* f,
+                      const int64_t* foff, double* l_out, double* c_out,
+                      double* mt_out) {
+    if (!valid_layout(P, L, hoff) || !valid_layout(P, L, foff) || m == NULL ||
+        l_out == NULL || c_out == NULL || N < 0 || B < 1)
+        return -1;
+    double* mt = mt_out;
+    if (mt == NULL) {
+        mt = (double*)malloc(sizeof(double) * (size_t)(P * N + 1));
+        if (mt == NULL) return -2;
+    }
+    for (int64_t t0 = 0; t0 < N; t0 += B) {
+        int64_t t1 = t0 + B < N ? t0 + B : N;
+        for (int p = 0; p < P; ++p)
+            for (int64_t t = t0; t < t1; ++t)
+                mt[(int64_t)p * N + t] =
+                    m[(int64_t)p * N + t] - (t >= B ? c_out[(int64_t)p * N + t - B] : 0.0);
+#pragma omp parallel for schedule(static)
+        for (int l = 0; l < L; ++l)
+            for (int64_t t = t0; t < t1; ++t) {
+                double s = 0.0;
+                for (int p = 0; p < P; ++p) {
+                    int64_t pi = (int64_t)p * L + l;
+                    s += pair_sample(mt + (int64_t)p * N, t1, h + hoff[pi],
+                                     hoff[pi + 1] - hoff[pi], t);
+                }
+                l_out[(int64_t)l * N + t] = s;
+            }
+#pragma omp parallel for schedule(static)
+        for (int p = 0; p < P; ++p)
+            for (int64_t t = t0; t < t1; ++t) {
+                double s = 0.0;
+                for (int l = 0; l < L; ++l) {
+                    int64_t pi = (int64_t)p * L + l;
+                    s += pair_sample(l_out + (int64_t)l * N, t1, f + foff[pi],
+                                     foff[pi + 1] - foff[pi], t);
+                }
+                c_out[(int64_t)p * N + t] = s;
+            }
+    }
+    if (mt_out == NULL) free(mt);
+    return 0;
 }

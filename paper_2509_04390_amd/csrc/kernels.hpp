@@ -40,7 +40,7 @@ namespace rta {
 
 constexpr int kThreads = 256;
 constexpr int kMaxTiers = 8;
-constexpr int kUnroll = 4;
+constexpr int kUnroll = 4;  // rows in flight per lane (FP32 spectra; half for 16-bit)
 
 enum ItemKind : int32_t {
   K_MAC = 0,    // k_block tail: multiply-accumulate of a partition range
@@ -231,12 +231,17 @@ __device__ void mac_item(const KArgs& A, const DevTier& T, const Item& it,
   const int step = RP % K;
   int p = it.p0 + s;
   int slot = wrap_slot(frame - p, K);
-  for (; p < it.p1; p += RP * kUnroll) {
-    float2 xv[kUnroll][C];
-    float2 hv[kUnroll][G][C];
+  // 16-bit spectra carry twice the bins per load; with a quarter of the rows
+  // in flight the registers stay low enough for every tail workgroup of the
+  // launch to be resident at once (measured: with half, some started only
+  // when others finished and the launch took 24 us instead of 18 us)
+  constexpr int U = C == 2 ? kUnroll : kUnroll / 4;
+  for (; p < it.p1; p += RP * U) {
+    float2 xv[U][C];
+    float2 hv[U][G][C];
     int sl = slot;
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int pu = p + u * RP;
       if (pu < it.p1) {
         load_x<C>(Xq + (int64_t)sl * P, xv[u]);
@@ -258,7 +263,7 @@ __device__ void mac_item(const KArgs& A, const DevTier& T, const Item& it,
     }
     slot = sl;
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u)
+    for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int g = 0; g < G; ++g)
 #pragma unroll
@@ -449,6 +454,69 @@ __device__ void head_work(const KArgs& A, const Group& grp, float2* lds) {
   const float2* tw = stage_twiddles(T, lds + L.tw);
   const HT* H01 = reinterpret_cast<const HT*>(A.H01);
 
+  // 0. Prefetch.  The heads run beside the bandwidth-bound tails, so every
+  //    global round trip is slow; everything that does not depend on this
+  //    block's FFT is requested up front into registers -- the first input
+  //    chunk's window samples and H_{l,q,0} coefficients, and the later
+  //    tiers' ring samples of this block -- so that its latency overlaps the
+  //    partial-sum loads of step 1.  (Sizes beyond the register budget fall
+  //    back to loading in place.)
+  constexpr int WMAX = 2, HMAX = 4, RMAX = 1, TMAX = 2;
+  const int E = grp.nl * P;
+  const int nb0 = min(A.head_nq, A.Q);
+  const int ept = (E + kThreads - 1) / kThreads;       // output elements per thread
+  const int half = P >> 1;
+  const int eo = grp.nl * half;                         // output sample pairs
+  const bool pre_w = nb0 * P <= WMAX * kThreads;
+  const bool pre_h = ept * nb0 <= HMAX;
+  const bool pre_r = A.n_tiers - 1 <= TMAX && eo <= RMAX * kThreads;
+  auto window = [&](int e, int q0) {
+    const int b = e / P, m = e - b * P;
+    const int q = q0 + b;
+    const float* hq = A.hist + (int64_t)q * (A.hist_mask + 1);
+    const float* iq = A.in + (int64_t)q * A.B;
+    const int i0 = 2 * m, i1 = 2 * m + 1;
+    const float w0 = i0 < P ? hq[((n - 1) * A.B + i0) & A.hist_mask] : iq[i0 - P];
+    const float w1 = i1 < P ? hq[((n - 1) * A.B + i1) & A.hist_mask] : iq[i1 - P];
+    return make_float2(w0, w1);
+  };
+  auto h0_at = [&](int e, int q) {
+    const int g = e / P, k = e - g * P;
+    return HVec<HT>::load1(H01 + ((int64_t)((grp.l0 + g) * A.Q + q) * 2) * P + k);
+  };
+  float2 wv[WMAX], hv[HMAX];
+  float rv[RMAX][TMAX][2];
+  if (pre_w) {
+#pragma unroll
+    for (int i = 0; i < WMAX; ++i) {
+      const int e = tid + i * kThreads;
+      if (e < nb0 * P) wv[i] = window(e, 0);
+    }
+  }
+  if (pre_h) {
+#pragma unroll
+    for (int i = 0; i < HMAX; ++i) {
+      const int ie = i / nb0, b = i - ie * nb0;
+      const int e = tid + ie * kThreads;
+      if (ie < ept && e < E) hv[i] = h0_at(e, b);
+    }
+  }
+  if (pre_r) {
+#pragma unroll
+    for (int i = 0; i < RMAX; ++i) {
+      const int e = tid + i * kThreads;
+#pragma unroll
+      for (int t = 0; t < TMAX; ++t) {
+        if (e < eo && t + 1 < A.n_tiers) {
+          const int g = e / half, j = 2 * (e - g * half);
+          const float* ring = A.tier[t + 1].oring + (int64_t)(grp.l0 + g) * (A.ring_mask + 1);
+          rv[i][t][0] = ring[(n * A.B + j) & A.ring_mask];
+          rv[i][t][1] = ring[(n * A.B + j + 1) & A.ring_mask];
+        }
+      }
+    }
+  }
+
   // 1. the terms p >= 2, summed by the previous launch's tail items, and the
   //    term p = 1 (ring slot n-1)
   const DevTier Tcur = [&] {
@@ -462,15 +530,14 @@ __device__ void head_work(const KArgs& A, const Group& grp, float2* lds) {
   const int slot0 = wrap_slot(n, T.K);
   for (int q0 = 0; q0 < A.Q; q0 += A.head_nq) {
     const int nb = min(A.head_nq, A.Q - q0);
-    for (int e = tid; e < nb * P; e += kThreads) {
-      const int b = e / P, m = e - b * P;
-      const int q = q0 + b;
-      const float* hq = A.hist + (int64_t)q * (A.hist_mask + 1);
-      const float* iq = A.in + (int64_t)q * A.B;
-      const int i0 = 2 * m, i1 = 2 * m + 1;
-      const float w0 = i0 < P ? hq[((n - 1) * A.B + i0) & A.hist_mask] : iq[i0 - P];
-      const float w1 = i1 < P ? hq[((n - 1) * A.B + i1) & A.hist_mask] : iq[i1 - P];
-      Xa[e] = make_float2(w0, w1);
+    if (q0 == 0 && pre_w) {
+#pragma unroll
+      for (int i = 0; i < WMAX; ++i) {
+        const int e = tid + i * kThreads;
+        if (e < nb * P) Xa[e] = wv[i];
+      }
+    } else {
+      for (int e = tid; e < nb * P; e += kThreads) Xa[e] = window(e, q0);
     }
     __syncthreads();
     float2* z = fft_stockham<false>(Xa, Xb, P, logP, tw, nb);
@@ -488,45 +555,84 @@ __device__ void head_work(const KArgs& A, const Group& grp, float2* lds) {
             A.in[(int64_t)q * A.B + i];
       }
     }
-    for (int e = tid; e < grp.nl * P; e += kThreads) {
-      const int g = e / P, k = e - g * P;
-      const int l = grp.l0 + g;
-      float2 acc = Y[e];
-      for (int b = 0; b < nb; ++b) {
-        const int q = q0 + b;
-        const HT* h = H01 + ((int64_t)(l * A.Q + q) * 2) * P + k;
-        const float2 h0 = HVec<HT>::load1(h);
+    if (q0 == 0 && pre_h) {
+      // register slot i holds element ie = i / nb, input b = i % nb (the
+      // same mapping as the prefetch); each element belongs to this thread
+#pragma unroll
+      for (int i = 0; i < HMAX; ++i) {
+        const int ie = i / nb, b = i - ie * nb;
+        const int e = tid + ie * kThreads;
+        if (ie >= ept || e >= E) continue;
+        const int k = e % P;
+        const float2 h0 = hv[i];
         const float2 x0 = x[b * P + k];
-        acc = cadd(acc, (k == 0) ? make_float2(h0.x * x0.x, h0.y * x0.y) : cmul(h0, x0));
+        Y[e] = cadd(Y[e], (k == 0) ? make_float2(h0.x * x0.x, h0.y * x0.y) : cmul(h0, x0));
       }
-      Y[e] = acc;
+    } else {
+      for (int e = tid; e < E; e += kThreads) {
+        const int k = e % P;
+        float2 acc = Y[e];
+        for (int b = 0; b < nb; ++b) {
+          const float2 h0 = h0_at(e, q0 + b);
+          const float2 x0 = x[b * P + k];
+          acc = cadd(acc, (k == 0) ? make_float2(h0.x * x0.x, h0.y * x0.y) : cmul(h0, x0));
+        }
+        Y[e] = acc;
+      }
     }
     __syncthreads();
   }
 
   // 3. inverse real FFT of the group's outputs, keep the last B samples, add
-  //    the later tiers' contributions from their output rings, emit
+  //    the later tiers' contributions from their output rings (and clear
+  //    them), emit
   irfft_pre(Y, Xa, P, tw + P, grp.nl);
   float2* z = fft_stockham<true>(Xa, Xb, P, logP, tw, grp.nl);
   const float scale = 1.0f / (float)(2 * P);
-  const int half = P >> 1;
-  for (int e = tid; e < grp.nl * half; e += kThreads) {
+  auto emit = [&](int e, float y0, float y1) {
     const int g = e / half, m = half + (e - g * half);
     const int l = grp.l0 + g;
-    const float2 v = z[g * P + m];
     const int i = 2 * (m - half);
-    float y0 = v.x * scale, y1 = v.y * scale;
+    const float2 v = z[g * P + m];
+    A.out[(int64_t)l * A.B + i] = y0 + v.x * scale;
+    A.out[(int64_t)l * A.B + i + 1] = y1 + v.y * scale;
+  };
+  auto clear_rings = [&](int e) {
+    const int g = e / half, j = 2 * (e - g * half);
     for (int t = 1; t < A.n_tiers; ++t) {
-      float* ring = A.tier[t].oring + (int64_t)l * (A.ring_mask + 1);
-      const int64_t s0 = (n * A.B + i) & A.ring_mask;
-      const int64_t s1 = (n * A.B + i + 1) & A.ring_mask;
-      y0 += ring[s0];
-      y1 += ring[s1];
-      ring[s0] = 0.f;
-      ring[s1] = 0.f;
+      float* ring = A.tier[t].oring + (int64_t)(grp.l0 + g) * (A.ring_mask + 1);
+      ring[(n * A.B + j) & A.ring_mask] = 0.f;
+      ring[(n * A.B + j + 1) & A.ring_mask] = 0.f;
     }
-    A.out[(int64_t)l * A.B + i] = y0;
-    A.out[(int64_t)l * A.B + i + 1] = y1;
+  };
+  if (pre_r) {
+#pragma unroll
+    for (int i = 0; i < RMAX; ++i) {
+      const int e = tid + i * kThreads;
+      if (e >= eo) continue;
+      float y0 = 0.f, y1 = 0.f;
+#pragma unroll
+      for (int t = 0; t < TMAX; ++t) {
+        if (t + 1 < A.n_tiers) {
+          y0 += rv[i][t][0];
+          y1 += rv[i][t][1];
+        }
+      }
+      emit(e, y0, y1);
+      clear_rings(e);
+    }
+  } else {
+    for (int e = tid; e < eo; e += kThreads) {
+      const int g = e / half, j = 2 * (e - g * half);
+      float y0 = 0.f, y1 = 0.f;
+      for (int t = 1; t < A.n_tiers; ++t) {
+        const float* ring = A.tier[t].oring + (int64_t)(grp.l0 + g) * (A.ring_mask + 1);
+        y0 += ring[(n * A.B + j) & A.ring_mask];
+        y1 += ring[(n * A.B + j + 1) & A.ring_mask];
+      }
+      emit(e, y0, y1);
+      clear_rings(e);
+    }
   }
 
   // 4. completion (rta_process only): every head makes its output visible

@@ -228,3 +228,75 @@ def test_fftols_with_absent_paths_and_zero_history():
 def test_error_db_definition():
     y = np.array([[3.0, 4.0]])
     assert oracle.error_db(y * (1 + 1e-5), y)[0] == pytest.approx(-100.0, abs=1e-6)
+
+
+# ----------------------------------------------------------------------------
+# Feedback-cancellation loop (Sec. III-A Eq. 3, Sec. V): mt = m - c delayed by
+# one block, l = H^T * mt, c = F-hat * l
+# ----------------------------------------------------------------------------
+
+def _rand_filters(r, P, L, n, scale=0.3):
+    return [[r.standard_normal(n) * scale for _ in range(L)] for _ in range(P)]
+
+
+def test_feedback_loop_without_feedback_is_plain_synthesis():
+    r = rng(30)
+    P, L, N, B = 2, 3, 700, 16
+    h = _rand_filters(r, P, L, 90)
+    zero = [[np.zeros(5) for _ in range(L)] for _ in range(P)]
+    m = r.standard_normal((P, N))
+    l, c, mt = oracle.feedback_loop(m, h, zero, B)
+    assert np.all(c == 0.0) and np.array_equal(mt, m)
+    for j in range(L):
+        want = sum(np.convolve(m[p], h[p][j])[:N] for p in range(P))
+        assert np.max(np.abs(l[j] - want)) < 1e-11
+
+
+def test_feedback_loop_gain_feedback_is_a_block_comb():
+    # H = delta, F-hat = a delta: mt[t] = m[t] - a mt[t - B], so an impulse
+    # gives mt[kB] = (-a)^k (exact: a = 1/2) and zero elsewhere.
+    B, a, N = 4, 0.5, 64
+    m = np.zeros((1, N))
+    m[0, 0] = 1.0
+    l, c, mt = oracle.feedback_loop(m, [[np.array([1.0])]], [[np.array([a])]], B)
+    want = np.zeros(N)
+    want[::B] = (-a) ** np.arange(N // B)
+    assert np.array_equal(mt[0], want)
+    assert np.array_equal(l[0], want)
+    assert np.array_equal(c[0], a * want)
+
+
+def test_feedback_loop_cancels_a_matched_room_exactly():
+    # Simulated room: the microphones hear the source s plus the loudspeaker
+    # signals through paths F, one block late.  With F-hat = F the loop removes
+    # them: mt = s and l = H^T * s.
+    r = rng(31)
+    P, L, N, B = 2, 3, 600, 8
+    # weak feedback paths keep the loop stable, as real ones are
+    h = _rand_filters(r, P, L, 50)
+    f = _rand_filters(r, P, L, 30, scale=0.01)
+    s = r.standard_normal((P, N))
+    l_star = np.array([sum(np.convolve(s[p], h[p][j])[:N] for p in range(P)) for j in range(L)])
+    fb = np.array([sum(np.convolve(l_star[j], f[p][j])[:N] for j in range(L)) for p in range(P)])
+    m = s.copy()
+    m[:, B:] += fb[:, :N - B]
+    l, c, mt = oracle.feedback_loop(m, h, f, B)
+    assert np.max(np.abs(mt - s)) < 1e-10
+    assert np.max(np.abs(l - l_star)) < 1e-10
+
+
+def test_feedback_loop_is_linear_and_block_causal():
+    r = rng(32)
+    P, L, N, B = 1, 2, 400, 32
+    h = _rand_filters(r, P, L, 70)
+    f = _rand_filters(r, P, L, 40, scale=0.01)
+    m1, m2 = r.standard_normal((P, N)), r.standard_normal((P, N))
+    l1 = oracle.feedback_loop(m1, h, f, B)[0]
+    l2 = oracle.feedback_loop(m2, h, f, B)[0]
+    l12 = oracle.feedback_loop(1.5 * m1 - 0.25 * m2, h, f, B)[0]
+    assert np.max(np.abs(l12 - (1.5 * l1 - 0.25 * l2))) < 1e-10
+    m3 = m1.copy()
+    m3[:, 5 * B:] = r.standard_normal((P, N - 5 * B))
+    l3 = oracle.feedback_loop(m3, h, f, B)[0]
+    assert np.array_equal(l3[:, :5 * B], l1[:, :5 * B])
+    assert not np.allclose(l3[:, 5 * B:], l1[:, 5 * B:])
