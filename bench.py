@@ -232,10 +232,14 @@ def main() -> int:
         f"(mean of {n_timed})")
     probes = read_probes(torch, rta, int(info["spectra_bytes"]), info["grid"], stream)
 
-    # synchronous host-memory blocks: per-block latency including PCIe
+    # synchronous host-memory blocks: per-block latency including PCIe (after
+    # a few untimed calls: the first use of the pinned buffers is slow)
     cv.reset()
     lat = []
     out = np.empty((L, B), np.float32)
+    for i in range(16):
+        rta.rta_process(cv.ctx, np.ascontiguousarray(x[:, i * B:(i + 1) * B]), out)
+    cv.reset()
     for i in range(args.latency_blocks):
         blk = np.ascontiguousarray(x[:, (i % nblk) * B:(i % nblk + 1) * B])
         t = time.perf_counter()

@@ -54,9 +54,9 @@ typedef enum rta_status {
 typedef enum rta_dtype { RTA_FP32 = 0, RTA_FP16 = 1, RTA_BF16 = 2 } rta_dtype;
 
 /* rta_create() flags. */
-#define RTA_FLAG_SPIKE   0x1u  /* NUPC: do a tier's whole frame in the block
-                                  its input completes (needs offset >= size-B
-                                  ... see rta_scheme); default spreads it.  */
+#define RTA_FLAG_SPIKE   0x1u  /* NUPC: accumulate each later-tier frame in
+                                  the single block after its FFT instead of
+                                  spreading it over the frame's slack.     */
 
 /* Partition scheme (Sec. III-B: uniform and non-uniform partitioning).
  *   size[t]  partition length of tier t in samples; size[0] must equal the
@@ -66,8 +66,11 @@ typedef enum rta_dtype { RTA_FP32 = 0, RTA_FP16 = 1, RTA_BF16 = 2 } rta_dtype;
  *            "as many as the longest filter needs".
  * Tier t covers filter taps [o_t, o_t + count[t]*size[t]) with o_0 = 0 and
  * o_{t+1} = o_t + count[t]*size[t].  For t >= 1 the scheme must satisfy
- * o_t >= 2*size[t] - block (the frame's work is then spread over the
- * size[t]/block blocks before its first output sample is due).
+ * o_t >= size[t] + block: a frame of tier t needs one block for its FFT and
+ * at least one for its multiply-accumulate before its first output sample
+ * is due.  The multiply-accumulate is spread over min(s, size[t]/block + 1)
+ * - 1 blocks, s = (o_t + block - size[t]) / block; o_t = 2*size[t] - block
+ * gives every tier s = size[t]/block.  Other schemes return RTA_E_ARG.
  * A NULL scheme means uniform partitioning with size[0] = block, i.e. the
  * paper's UPOLS with n_k = n_x and n_f = 2 n_x (Sec. IV). */
 typedef struct rta_scheme {
@@ -194,6 +197,21 @@ int rta_process(rta_ctx* ctx, const float* in, float* out);
  * a launch captured into a graph and replayed would repeat the same block. */
 int rta_process_device(rta_ctx* ctx, const float* d_in, float* d_out,
                        void* stream);
+
+/* Feedback cancellation (Sec. III-A Eq. 3, Sec. V).  fb[q*n_out + l] points
+ * to lengths[q*n_out + l] FP32 taps of f_ql, the estimated acoustic path
+ * from output (loudspeaker) l to input (microphone) q -- row-major
+ * [in][out] like the synthesis filters; NULL or length 0 means no path.
+ * From then on block n's input is m_n - c_{n-1}: the feedback estimate
+ * c = F * y, computed from the context's own output y by a second,
+ * uniformly partitioned convolution (partition = block) on the GPU, is
+ * subtracted from the next block of microphone samples.  That convolution is
+ * launched on the same stream after each block's output is complete, so it
+ * is not on rta_process's latency path.  fb == NULL removes the feedback
+ * paths.  Resets the context (as rta_reset).  Taps are copied during the
+ * call. */
+int rta_set_feedback(rta_ctx* ctx, const float* const* fb, const int64_t* lengths,
+                     int32_t spectra);
 
 /* Zero all delay lines, input history, output rings and the block index, as
  * if the context had just been created.  Synchronous. */

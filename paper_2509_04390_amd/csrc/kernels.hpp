@@ -110,6 +110,8 @@ struct KArgs {
   const void* H01;           // [L][Q][2][P] spectra of partitions 0 and 1
   unsigned int* head_count;  // heads finished in this launch (zero between)
   int64_t* done_flag;        // host-visible: n + 1 once the output is written
+  const float* sub;          // feedback estimate [Q][B] subtracted from `in`
+  float* out2;               // second copy of the output block (feedback input)
 };
 
 // ---------------------------------------------------------------------------
@@ -476,8 +478,15 @@ __device__ void head_work(const KArgs& A, const Group& grp, float2* lds) {
     const float* hq = A.hist + (int64_t)q * (A.hist_mask + 1);
     const float* iq = A.in + (int64_t)q * A.B;
     const int i0 = 2 * m, i1 = 2 * m + 1;
-    const float w0 = i0 < P ? hq[((n - 1) * A.B + i0) & A.hist_mask] : iq[i0 - P];
-    const float w1 = i1 < P ? hq[((n - 1) * A.B + i1) & A.hist_mask] : iq[i1 - P];
+    float w0, w1;
+    if (A.sub == nullptr) {
+      w0 = i0 < P ? hq[((n - 1) * A.B + i0) & A.hist_mask] : iq[i0 - P];
+      w1 = i1 < P ? hq[((n - 1) * A.B + i1) & A.hist_mask] : iq[i1 - P];
+    } else {  // microphone minus the previous block's feedback estimate
+      const float* sq = A.sub + (int64_t)q * A.B;
+      w0 = i0 < P ? hq[((n - 1) * A.B + i0) & A.hist_mask] : iq[i0 - P] - sq[i0 - P];
+      w1 = i1 < P ? hq[((n - 1) * A.B + i1) & A.hist_mask] : iq[i1 - P] - sq[i1 - P];
+    }
     return make_float2(w0, w1);
   };
   auto h0_at = [&](int e, int q) {
@@ -552,7 +561,7 @@ __device__ void head_work(const KArgs& A, const Group& grp, float2* lds) {
         const int b = e / A.B, i = e - b * A.B;
         const int q = q0 + b;
         A.hist[(int64_t)q * (A.hist_mask + 1) + ((n * A.B + i) & A.hist_mask)] =
-            A.in[(int64_t)q * A.B + i];
+            A.in[(int64_t)q * A.B + i] - (A.sub ? A.sub[(int64_t)q * A.B + i] : 0.f);
       }
     }
     if (q0 == 0 && pre_h) {
@@ -594,8 +603,13 @@ __device__ void head_work(const KArgs& A, const Group& grp, float2* lds) {
     const int l = grp.l0 + g;
     const int i = 2 * (m - half);
     const float2 v = z[g * P + m];
-    A.out[(int64_t)l * A.B + i] = y0 + v.x * scale;
-    A.out[(int64_t)l * A.B + i + 1] = y1 + v.y * scale;
+    const float o0 = y0 + v.x * scale, o1 = y1 + v.y * scale;
+    A.out[(int64_t)l * A.B + i] = o0;
+    A.out[(int64_t)l * A.B + i + 1] = o1;
+    if (A.out2 != nullptr) {
+      A.out2[(int64_t)l * A.B + i] = o0;
+      A.out2[(int64_t)l * A.B + i + 1] = o1;
+    }
   };
   auto clear_rings = [&](int e) {
     const int g = e / half, j = 2 * (e - g * half);

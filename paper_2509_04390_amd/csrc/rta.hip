@@ -97,6 +97,10 @@ struct rta_ctx {
   float* m_out = nullptr;
   int64_t* m_flag = nullptr;
 
+  rta_ctx* fc = nullptr;        // feedback convolution: outputs -> inputs
+  float* d_y = nullptr;         // [L][B] copy of the output block (its input)
+  float* d_c = nullptr;         // [Q][B] its output, subtracted next block
+
   bool poisoned = false;
   bool timing = false;
   std::vector<hipEvent_t> events;  // 2 per timed block
@@ -595,11 +599,22 @@ int launch_block(rta_ctx* c, const float* in, float* out, hipStream_t s, bool fl
     c->events_used += 2;
     HIP_TRY(c, hipEventRecord(e[0], s));
   }
+  if (c->fc != nullptr) {
+    a.sub = c->d_c;
+    a.out2 = c->d_y;
+  }
   hipLaunchKernelGGL(block_kernel(c->dtype, c->G), dim3(grid), dim3(kThreads), c->lds, s, a);
   HIP_TRY(c, hipGetLastError());
   if (n_tier > 0) {
     hipLaunchKernelGGL(tier_kernel(c->G), dim3(n_tier), dim3(kThreads), c->lds_tier, s, a);
     HIP_TRY(c, hipGetLastError());
+  }
+  if (c->fc != nullptr) {  // feedback estimate of this block, for the next one
+    const int st = launch_block(c->fc, c->d_y, c->d_c, s);
+    if (st != RTA_OK) {
+      c->poisoned = true;
+      return st;
+    }
   }
   if (e) HIP_TRY(c, hipEventRecord(e[1], s));
   c->block += 1;
@@ -619,7 +634,12 @@ int zero_state(rta_ctx* c) {
   }
   HIP_TRY(c, hipMemsetAsync(c->hist, 0, sizeof(float) * (size_t)c->Q * c->hist_len, c->stream));
   HIP_TRY(c, hipMemsetAsync(c->head_count, 0, sizeof(unsigned int), c->stream));
+  if (c->d_c) HIP_TRY(c, hipMemsetAsync(c->d_c, 0, sizeof(float) * (size_t)c->Q * c->B, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (c->fc) {
+    const int st = zero_state(c->fc);
+    if (st != RTA_OK) return st;
+  }
   __atomic_store_n(c->h_flag, (int64_t)0, __ATOMIC_RELEASE);
   c->block = 0;
   return RTA_OK;
@@ -871,6 +891,11 @@ int create_impl(rta_ctx* c, const std::vector<int>& size, const std::vector<int>
 
 void free_all(rta_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  if (c->fc) {
+    free_all(c->fc);
+    delete c->fc;
+    c->fc = nullptr;
+  }
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
   c->events.clear();
   for (void* p : c->dev_allocs) (void)hipFree(p);
@@ -1062,6 +1087,41 @@ int rta_query(rta_ctx* c, rta_info* info) {
   info->rows_per_item = c->rows_per_item;
   info->poisoned = c->poisoned ? 1 : 0;
   return c->poisoned ? RTA_E_DEVICE : RTA_OK;
+}
+
+int rta_set_feedback(rta_ctx* c, const float* const* fb, const int64_t* lengths, int32_t spectra) {
+  if (c == nullptr) return RTA_E_ARG;
+  if (c->poisoned) return RTA_E_DEVICE;
+  HIP_TRY(c, hipDeviceSynchronize());
+  if (c->fc) {
+    free_all(c->fc);
+    delete c->fc;
+    c->fc = nullptr;
+  }
+  if (fb != nullptr) {
+    if (lengths == nullptr) return RTA_E_ARG;
+    // the feedback convolution runs outputs -> inputs: its filter [l][q]
+    // is f_ql
+    const int64_t np = (int64_t)c->Q * c->L;
+    std::vector<const float*> ft(np);
+    std::vector<int64_t> lt(np);
+    for (int q = 0; q < c->Q; ++q)
+      for (int l = 0; l < c->L; ++l) {
+        ft[(int64_t)l * c->Q + q] = fb[(int64_t)q * c->L + l];
+        lt[(int64_t)l * c->Q + q] = lengths[(int64_t)q * c->L + l];
+      }
+    rta_ctx* fc = nullptr;
+    const int st = rta_create_tuned(&fc, c->fs, c->B, nullptr, c->L, c->Q, ft.data(), lt.data(),
+                                    spectra, 0, nullptr);
+    if (st != RTA_OK) return st;
+    c->fc = fc;
+    if (c->d_y == nullptr) {
+      int s2;
+      if ((s2 = dev_alloc(c, &c->d_y, (size_t)c->L * c->B)) != RTA_OK) return s2;
+      if ((s2 = dev_alloc(c, &c->d_c, (size_t)c->Q * c->B)) != RTA_OK) return s2;
+    }
+  }
+  return zero_state(c);
 }
 
 int rta_timing_enable(rta_ctx* c, int32_t on) {

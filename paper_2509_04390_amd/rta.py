@@ -43,7 +43,8 @@ RTA_MAX_TIERS = 8
 
 EXPORTED = ("rta_create", "rta_process", "rta_process_device", "rta_reset",
             "rta_query", "rta_timing_enable", "rta_timing_read", "rta_probe_read",
-            "rta_destroy", "rta_strerror", "rta_create_tuned", "rta_autotune")
+            "rta_destroy", "rta_strerror", "rta_create_tuned", "rta_autotune",
+            "rta_set_feedback")
 
 
 class rta_scheme(ctypes.Structure):
@@ -97,6 +98,8 @@ _lib.rta_autotune.argtypes = [ctypes.c_double, ctypes.c_int32, ctypes.POINTER(rt
                               ctypes.c_int32, ctypes.POINTER(rta_tuning),
                               ctypes.POINTER(ctypes.c_double)]
 _lib.rta_process.argtypes = [ctypes.c_void_p, _fp, _fp]
+_lib.rta_set_feedback.argtypes = [ctypes.c_void_p, ctypes.POINTER(_fp),
+                                  ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]
 _lib.rta_process_device.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_void_p]
 _lib.rta_reset.argtypes = [ctypes.c_void_p]
@@ -111,7 +114,7 @@ _lib.rta_strerror.argtypes = [ctypes.c_int]
 _lib.rta_strerror.restype = ctypes.c_char_p
 for _f in ("rta_create", "rta_process", "rta_process_device", "rta_reset", "rta_query",
            "rta_timing_enable", "rta_timing_read", "rta_probe_read", "rta_destroy",
-           "rta_create_tuned", "rta_autotune"):
+           "rta_create_tuned", "rta_autotune", "rta_set_feedback"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -230,6 +233,17 @@ def rta_process_device(ctx, d_in: int, d_out: int, stream: int = 0) -> None:
                                    ctypes.c_void_p(stream or None)), "rta_process_device")
 
 
+def rta_set_feedback(ctx, n_in: int, n_out: int, feedback, spectra="fp32") -> None:
+    """feedback: n_in x n_out nested list of FP32 taps f_ql (output l to input
+    q), None/empty = no path; feedback=None removes the paths."""
+    if feedback is None:
+        _check(_lib.rta_set_feedback(ctx, None, None, 0), "rta_set_feedback")
+        return
+    keep, ptrs, lens, _ = _marshal(feedback, n_in, n_out, None, None)
+    dtype = DTYPES[spectra] if isinstance(spectra, str) else int(spectra)
+    _check(_lib.rta_set_feedback(ctx, ptrs, lens, dtype), "rta_set_feedback")
+
+
 def rta_reset(ctx) -> None:
     _check(_lib.rta_reset(ctx), "rta_reset")
 
@@ -317,6 +331,10 @@ class Convolver:
 
     def reset(self):
         rta_reset(self.ctx)
+
+    def set_feedback(self, feedback, spectra="fp32"):
+        """Estimated feedback paths f_ql (output l -> input q), Q x L nested."""
+        rta_set_feedback(self.ctx, self.n_in, self.n_out, feedback, spectra)
 
     def process(self, block_in: np.ndarray) -> np.ndarray:
         out = np.empty((self.n_out, self.block), np.float32)
