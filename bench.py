@@ -129,6 +129,122 @@ def copy_probe(mb: int, reps: int) -> None:
     print(json.dumps({"copy_probe_bytes": n * 4, "reps": reps}))
 
 
+def serve_bench(args, torch, rta, workloads) -> dict:
+    """Serving with continuous batching: 16 source slots -> 64 outputs, 12 s
+    filters, block 64.  Sources arrive as a Poisson process and stay for
+    exponentially distributed times; a control thread admits and releases
+    them (admission by HBM arena and per-block bandwidth budget) while the
+    main thread issues one synchronous host-memory block every B/fs."""
+    import threading
+    wl = workloads.config("serve")
+    B, L, taps, fs = wl.block, wl.n_out, wl.lengths, float(wl.fs)
+    spectra = args.spectra or wl.dtype
+    scheme = None
+    if args.scheme and args.scheme != "uniform":
+        scheme = [tuple(int(v) for v in t.split("x")) for t in args.scheme.split(",")]
+    n_blocks = int(args.serve_seconds * fs / B)
+    period = B / fs
+    rng = np.random.default_rng(wl.seed)
+    arrivals, t = [], 0.0
+    while True:
+        t += rng.exponential(1.0 / args.serve_rate)
+        if t >= args.serve_seconds:
+            break
+        life = rng.exponential(args.serve_life)
+        arrivals.append((int(t / period), int((t + life) / period), len(arrivals) % 4))
+    log(f"serve: {len(arrivals)} arrivals over {args.serve_seconds} s, {n_blocks} blocks")
+    pool = [workloads.reverb_filters(wl.seed + i, 1, L, taps, wl.rt60)[0] for i in range(4)]
+    stream = torch.cuda.current_stream()
+    probe = read_probes(torch, rta, 1 << 30, 1024, stream)["1GiB"]["gbs"]
+    budget = period * probe * 1e9 * args.serve_budget_frac
+    srv = rta.Server(wl.n_in, L, taps, B, fs=fs, scheme=scheme, spectra=spectra,
+                     budget_bytes=budget)
+    info0, _ = srv.query()
+    log(f"arena {info0['arena_bytes'] / 1e9:.2f} GB, budget {budget / 1e9:.2f} GB/block")
+
+    events = sorted([(a, 0, i) for i, (a, _, _) in enumerate(arrivals)] +
+                    [(e, 1, i) for i, (_, e, _) in enumerate(arrivals)])
+    state = {"block": 0, "done": False}
+    slot_of, admit_ms, outcome = {}, [], {"admitted": 0, "capacity": 0, "memory": 0}
+
+    def control():
+        for blk, kind, i in events:
+            while state["block"] < blk and not state["done"]:
+                time.sleep(0.0002)
+            if state["done"]:
+                return
+            if kind == 0:
+                t0 = time.perf_counter()
+                try:
+                    slot_of[i] = srv.admit(pool[arrivals[i][2]])
+                    admit_ms.append(1e3 * (time.perf_counter() - t0))
+                    outcome["admitted"] += 1
+                except rta.RtaError as e:
+                    outcome["memory" if e.status == rta.RTA_E_NOMEM else "capacity"] += 1
+            elif i in slot_of:
+                srv.release(slot_of.pop(i))
+
+    noise = workloads.white_noise(wl.seed + 1, wl.n_in, 256 * B)
+    blocks = [np.ascontiguousarray(noise[:, k * B:(k + 1) * B]) for k in range(256)]
+    out = np.empty((L, B), np.float32)
+    for k in range(16):  # first use of the pinned buffers
+        rta.rta_process(srv.ctx, blocks[k], out)
+    srv.reset()
+    th = threading.Thread(target=control, daemon=True)
+    th.start()
+    lat, live, mbpb = [], [], []
+    nxt = time.perf_counter()
+    for n in range(n_blocks):
+        nxt += period
+        state["block"] = n
+        t0 = time.perf_counter()
+        rta.rta_process(srv.ctx, blocks[n % 256], out)
+        lat.append(time.perf_counter() - t0)
+        if n % 50 == 0:
+            inf, _ = srv.query()
+            live.append(inf["live"])
+            mbpb.append(inf["bytes_per_block"] / 1e6)
+        if n % 3000 == 0:
+            log(f"  block {n}: live {live[-1]}, {mbpb[-1]:.0f} MB/block")
+        rem = nxt - time.perf_counter()
+        if rem > 3e-4:
+            time.sleep(rem - 2e-4)
+        while time.perf_counter() < nxt:
+            pass
+    state["done"] = True
+    th.join()
+    info, _ = srv.query()
+    srv.close()
+    lat_us = np.array(lat) * 1e6
+    deadline = rta.deadline_us(B, fs)
+    p99 = float(np.percentile(lat_us, 99))
+    return {
+        "metric": "serving: p99 block latency under continuous batching, 16 slots x 64 out x 12 s, B=64",
+        "value": p99, "unit": "us", "n_gpus": 1, "steps": n_blocks, "warmup": 16,
+        "ms_per_step": float(np.mean(lat_us)) / 1e3, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if spectra == "fp32" else f"f32 (spectra {spectra})", "data": "synthetic",
+        "config": {"workload": (f"serve: {wl.n_in} slots -> {L} out, {taps}-tap ({taps / fs:.0f} s) "
+                                f"filters, block {B}, {spectra} spectra, "
+                                f"{'uniform partitions' if scheme is None else args.scheme}; "
+                                f"Poisson arrivals {args.serve_rate}/s, Exp({args.serve_life} s) "
+                                f"lifetimes, {args.serve_seconds} s"),
+                   "block": B, "n_in": wl.n_in, "n_out": L, "taps": taps, "spectra": spectra},
+        "deadline_us": deadline,
+        "latency": {"p50_us": float(np.percentile(lat_us, 50)), "p99_us": p99,
+                    "max_us": float(lat_us.max()), "xruns": int(np.sum(lat_us > deadline)),
+                    "mode": "rta_process paced every B/fs, host memory, PCIe included"},
+        "serve": {"arrivals": len(arrivals), "admitted": outcome["admitted"],
+                  "refused_capacity": outcome["capacity"], "refused_memory": outcome["memory"],
+                  "live_mean": float(np.mean(live)), "live_max": int(np.max(live)),
+                  "mb_per_block_mean": float(np.mean(mbpb)), "mb_per_block_max": float(np.max(mbpb)),
+                  "budget_mb_per_block": budget / 1e6, "read_probe_gbs": probe,
+                  "admit_ms_p50": float(np.percentile(admit_ms, 50)) if admit_ms else None,
+                  "admit_ms_max": float(np.max(admit_ms)) if admit_ms else None,
+                  "plan_swaps": info["plan_swaps"], "arena_gb": info["arena_bytes"] / 1e9},
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,6 +264,13 @@ def main() -> int:
     ap.add_argument("--copy-probe-mb", type=int, default=0)
     ap.add_argument("--autotune", action="store_true",
                     help="run the library's autotuner first and use its scheme and tiling")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving with continuous batching (16 slots x 64 out x 12 s, B=64)")
+    ap.add_argument("--serve-seconds", type=float, default=20.0)
+    ap.add_argument("--serve-rate", type=float, default=8.0, help="arrivals per second")
+    ap.add_argument("--serve-life", type=float, default=2.0, help="mean source lifetime, s")
+    ap.add_argument("--serve-budget-frac", type=float, default=0.5,
+                    help="admission budget: this fraction of deadline x probed bandwidth")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -166,6 +289,10 @@ def main() -> int:
         return 0
 
     from paper_2509_04390_amd import rta, workloads
+
+    if args.serve:
+        print(json.dumps(serve_bench(args, torch, rta, workloads)))
+        return 0
 
     wl = workloads.config(args.workload)
     if args.spectra is None:

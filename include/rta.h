@@ -20,8 +20,9 @@
  * Conventions for every entry point:
  *   - Return value: RTA_OK (0) or a negative rta_status.  No exception or
  *     signal crosses the ABI; rta_strerror() names the code.
- *   - A context is used by one host thread at a time.  Distinct contexts are
- *     independent and may be used from different threads.
+ *   - A context is used by one host thread at a time (serving contexts also
+ *     accept one control thread, see rta_serve_create).  Distinct contexts
+ *     are independent and may be used from different threads.
  *   - After RTA_E_DEVICE the context is poisoned: every later call except
  *     rta_query/rta_destroy returns RTA_E_DEVICE.
  *   - Argument validation happens before any HIP call, so RTA_E_ARG never
@@ -45,7 +46,9 @@ typedef enum rta_status {
     RTA_E_RANGE = -3,       /* a filter spectrum exceeds the FP16 range      */
     RTA_E_DEVICE = -4,      /* a HIP runtime call failed; context poisoned   */
     RTA_E_STATE = -5,       /* call not valid in the context's current state */
-    RTA_E_UNSUPPORTED = -6  /* valid request this build does not implement   */
+    RTA_E_UNSUPPORTED = -6, /* valid request this build does not implement   */
+    RTA_E_CAPACITY = -7     /* serving: no free slot, or the per-block
+                               bandwidth budget would be exceeded           */
 } rta_status;
 
 /* Storage type of the filter spectra.  Input spectra, the multiply-
@@ -241,6 +244,108 @@ int rta_timing_read(rta_ctx* ctx, int64_t* blocks, double* kernel_ms);
  * pattern.  Returns RTA_E_DEVICE if the launch fails. */
 int rta_probe_read(const void* d_buf, int64_t bytes, int32_t grid, float* d_sink,
                    void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Serving with continuous batching.
+ *
+ * A serving context is a context with n_slots inputs whose filters are not
+ * fixed at creation: sources (a talker's or instrument's signal with its own
+ * filters to every output, i.e. one row h_q. of Eq. 1's filter matrix) are
+ * admitted into free slots and released while blocks keep streaming, and
+ * all live sources are convolved and mixed into the n_out outputs by the same
+ * one-launch-per-block path as rta_create()'s contexts (Eq. 2 over the live
+ * slots).  rta_process() and rta_process_device() take [n_slots][block]
+ * input; the rows of slots that are not live are ignored (read as zero).
+ *
+ * Admission (rta_serve_admit) is refused when
+ *   - no slot is free                         -> RTA_E_CAPACITY,
+ *   - the spectra do not fit in the HBM arena -> RTA_E_NOMEM,
+ *   - the filter-spectrum and delay-line bytes streamed per block by all
+ *     present sources plus the new one would exceed budget_bytes
+ *                                              -> RTA_E_CAPACITY.
+ * The new source's spectra are built on a separate stream into arena rows no
+ * block reads, then the source joins at the next block boundary: the next
+ * block launched reads its slot's input row (rta_serve_query reports that
+ * block as start_block).  Work lists are double-buffered: the next block
+ * switches to the new list, blocks in flight keep the old one.
+ *
+ * Release (rta_serve_release) stops the slot's input at the next block
+ * boundary (stop_block); the slot keeps streaming its filters until every
+ * delay line, history sample and partial sum it owns has returned to zero
+ * (free_block), then becomes free and its arena rows are reused.
+ * Its output tail (the filter's reverberation) is thus played out in full.
+ *
+ * Threads: one thread may run rta_process / rta_process_device while one
+ * other thread calls rta_serve_admit / rta_serve_release / rta_serve_query;
+ * the block thread only takes a short lock at each block boundary.
+ * rta_set_feedback and rta_autotune are not available for serving contexts
+ * (RTA_E_UNSUPPORTED); rta_reset zeroes all state, keeps live sources and
+ * frees released ones.
+ * ------------------------------------------------------------------------ */
+typedef struct rta_serve_config {
+    int32_t n_slots;       /* source slots (inputs), >= 1                   */
+    int32_t n_out;         /* outputs, >= 1                                 */
+    int64_t max_taps;      /* longest filter a source may bring, >= 1       */
+    int64_t arena_bytes;   /* HBM for filter spectra; 0 = room for every
+                              slot at max_taps on every output              */
+    double  budget_bytes;  /* admission limit on spectrum + delay-line bytes
+                              streamed per block by all present sources
+                              (e.g. deadline x attainable bandwidth x a
+                              safety factor); 0 = no limit                  */
+} rta_serve_config;
+
+typedef enum rta_slot_state {
+    RTA_SLOT_FREE = 0,
+    RTA_SLOT_JOINING = 1,   /* admitted; live from the next block           */
+    RTA_SLOT_LIVE = 2,
+    RTA_SLOT_LEAVING = 3,   /* released; input stops at the next block      */
+    RTA_SLOT_DRAINING = 4   /* input stopped; tail still streaming          */
+} rta_slot_state;
+
+typedef struct rta_slot_info {
+    int32_t state;              /* rta_slot_state                           */
+    int32_t pad;
+    int64_t start_block;        /* first block that read its input, or -1   */
+    int64_t stop_block;         /* first block that ignored it, or -1       */
+    int64_t free_block;         /* block from which the slot is free, or -1 */
+    int64_t taps;               /* longest of its filters                   */
+    double  bytes_per_block;    /* spectrum + delay-line bytes it streams   */
+} rta_slot_info;
+
+typedef struct rta_serve_info {
+    int32_t n_slots, live, draining, free_slots;
+    int64_t arena_bytes, arena_used_bytes;
+    double  budget_bytes, bytes_per_block;  /* present sources            */
+    int64_t admitted, rejected_slots, rejected_memory, rejected_budget;
+    int64_t plan_swaps;         /* work-list switches at block boundaries   */
+} rta_serve_info;
+
+/* Create a serving context with no source admitted.  fs, block, scheme,
+ * spectra, flags and tuning as for rta_create_tuned() (tuning may be NULL);
+ * the scheme's tiers and the tiling are laid out for n_slots sources of
+ * max_taps taps, so admissions never re-tile.  Allocates the spectra arena,
+ * delay lines, partial sums and both work-list buffers up front. */
+int rta_serve_create(rta_ctx** out, double fs, int32_t block,
+                     const rta_scheme* scheme, const rta_serve_config* cfg,
+                     int32_t spectra, uint32_t flags, const rta_tuning* tuning);
+
+/* Admit a source.  filters[l] points to lengths[l] FP32 taps of its filter
+ * to output l (n_out entries; NULL or length 0 = no path; every length
+ * <= max_taps).  On success *slot receives the slot index whose input row
+ * carries the source from the next block on.  Taps are copied during the
+ * call, which returns after the spectra are built (milliseconds) without
+ * waiting for the block thread.  Errors: see above; RTA_E_RANGE as for
+ * rta_create. */
+int rta_serve_admit(rta_ctx* ctx, const float* const* filters,
+                    const int64_t* lengths, int32_t* slot);
+
+/* Release the source in `slot` (JOINING or LIVE; else RTA_E_STATE). */
+int rta_serve_release(rta_ctx* ctx, int32_t slot);
+
+/* Counters of a serving context, and per-slot state when `slots` is not
+ * NULL (n_slots entries).  No device call.  RTA_E_STATE for a context
+ * made by rta_create(). */
+int rta_serve_query(rta_ctx* ctx, rta_serve_info* info, rta_slot_info* slots);
 
 /* Release the context and all its memory.  NULL is accepted (no-op). */
 int rta_destroy(rta_ctx* ctx);

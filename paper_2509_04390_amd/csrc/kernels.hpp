@@ -112,6 +112,8 @@ struct KArgs {
   int64_t* done_flag;        // host-visible: n + 1 once the output is written
   const float* sub;          // feedback estimate [Q][B] subtracted from `in`
   float* out2;               // second copy of the output block (feedback input)
+  const int32_t* live;       // [Q] serving: 0 = the slot's input reads as zero
+                             // (null: every input is live)
 };
 
 // ---------------------------------------------------------------------------
@@ -487,6 +489,10 @@ __device__ void head_work(const KArgs& A, const Group& grp, float2* lds) {
       w0 = i0 < P ? hq[((n - 1) * A.B + i0) & A.hist_mask] : iq[i0 - P] - sq[i0 - P];
       w1 = i1 < P ? hq[((n - 1) * A.B + i1) & A.hist_mask] : iq[i1 - P] - sq[i1 - P];
     }
+    if (A.live != nullptr && A.live[q] == 0) {  // a select, so NaN input stays out
+      if (i0 >= P) w0 = 0.f;
+      if (i1 >= P) w1 = 0.f;
+    }
     return make_float2(w0, w1);
   };
   auto h0_at = [&](int e, int q) {
@@ -560,8 +566,9 @@ __device__ void head_work(const KArgs& A, const Group& grp, float2* lds) {
       for (int e = tid; e < nb * A.B; e += kThreads) {
         const int b = e / A.B, i = e - b * A.B;
         const int q = q0 + b;
+        const float v = A.in[(int64_t)q * A.B + i] - (A.sub ? A.sub[(int64_t)q * A.B + i] : 0.f);
         A.hist[(int64_t)q * (A.hist_mask + 1) + ((n * A.B + i) & A.hist_mask)] =
-            A.in[(int64_t)q * A.B + i] - (A.sub ? A.sub[(int64_t)q * A.B + i] : 0.f);
+            (A.live != nullptr && A.live[q] == 0) ? 0.f : v;
       }
     }
     if (q0 == 0 && pre_h) {

@@ -20,11 +20,13 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
 
 #include "rta.h"
+#include "arena.hpp"
 #include "kernels.hpp"
 
 using namespace rta;
@@ -39,6 +41,7 @@ constexpr size_t kMaxTimedBlocks = 65536;
 
 struct TierHost {
   int P = 0, logP = 0, K = 0, count = 0;
+  int kcap = 0;  // serving: partitions of a max_taps filter in this tier
   int64_t offset = 0;
   void* H = nullptr;
   int64_t* pair_row = nullptr;
@@ -60,6 +63,8 @@ int ilog2(int64_t v) {
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
 }  // namespace
+
+struct Serve;
 
 struct rta_ctx {
   int device = 0;
@@ -101,6 +106,10 @@ struct rta_ctx {
   float* d_y = nullptr;         // [L][B] copy of the output block (its input)
   float* d_c = nullptr;         // [Q][B] its output, subtracted next block
 
+  const int32_t* live = nullptr;  // serving: [Q] live mask of the active list
+  int grid_items = 0;             // tail part of the grid
+  Serve* serve = nullptr;         // serving state (rta_serve_create)
+
   bool poisoned = false;
   bool timing = false;
   std::vector<hipEvent_t> events;  // 2 per timed block
@@ -108,6 +117,49 @@ struct rta_ctx {
   int64_t device_bytes = 0, spectra_bytes = 0;
   double h_bytes = 0, x_bytes = 0, io_bytes = 0, cmacs = 0, tail_bytes = 0;
   std::vector<void*> dev_allocs;
+};
+
+// Serving state (rta_serve_*; the protocol is described in include/rta.h).
+struct ServeSlot {
+  int state = RTA_SLOT_FREE;
+  bool rows_held = false;  // arena rows not yet returned
+  int64_t start = -1, stop = -1, free_at = -1, taps = 0;
+  double hb = 0, xb = 0, cm = 0;           // per-block figures of the source
+  std::vector<int64_t> row[kMaxTiers];     // [l] first arena row, -1 = none
+  std::vector<int32_t> kp[kMaxTiers];      // [l] partitions
+};
+
+struct PlanDev {  // one of the two work-list buffers
+  Item* items = nullptr;
+  int32_t* phase_count = nullptr;
+  Item* tier_items = nullptr;
+  int32_t* tier_count = nullptr;
+  int64_t* pair_row[kMaxTiers] = {};
+  int32_t* pair_K[kMaxTiers] = {};
+  int32_t* live = nullptr;
+  std::vector<int32_t> tier_count_host;
+  int grid_items = 0;
+  double hb = 0, xb = 0, cm = 0, tb = 0;
+};
+
+struct Serve {
+  rta_serve_config cfg{};
+  std::vector<ServeSlot> slots;
+  rta::RowArena arena[kMaxTiers];
+  PlanDev dev[2];
+  int active = 0;        // buffer the next launch uses
+  bool pending = false;  // the other buffer holds a newer list
+  hipEvent_t retire[2] = {nullptr, nullptr};
+  bool retire_valid[2] = {false, false};
+  hipStream_t aux = nullptr;  // spectra and list uploads
+  float* d_stage = nullptr;
+  int64_t stage_floats = 0;
+  SpecRow* d_rows = nullptr;
+  int64_t row_cap = 0;
+  int* d_range = nullptr;
+  std::mutex mu;   // slot states, active/pending; held briefly
+  std::mutex ctl;  // serializes admit, release and reset
+  int64_t admitted = 0, rej_slots = 0, rej_mem = 0, rej_budget = 0, swaps = 0;
 };
 
 namespace {
@@ -339,6 +391,7 @@ int build_plan(rta_ctx* c, Plan& plan) {
   const int G = c->G;
   const int C = vec_bins(c->dtype);
   const int ngroups = (c->L + G - 1) / G;
+  const bool fixed = c->serve != nullptr;
   const int n_phase = c->tier[c->n_tiers - 1].P / c->B;
   c->n_phase = n_phase;
   plan.block.assign(n_phase, {});
@@ -366,25 +419,35 @@ int build_plan(rta_ctx* c, Plan& plan) {
     int64_t total_rows = 0;
     for (const Group& gr : plan.groups)
       for (int q = 0; q < c->Q; ++q) total_rows += std::max(0, group_rows(T, gr, q) - 2);
+    // serving: every (group, input) owns the slots of a max_taps filter, so
+    // a slot's meaning does not depend on which sources are present
+    const int cap_rows = fixed ? std::max(0, T.kcap - 2) : 0;
+    if (fixed) total_rows = (int64_t)ngroups * c->Q * cap_rows;
     int R = c->rows_per_item;
     if (R <= 0) {
       const int64_t target_items = std::max(1, c->tail_items);
       R = (int)std::max<int64_t>(8, (total_rows * nslice + target_items - 1) / target_items);
     }
     c->rows_per_item = R;
+    const int nch_cap = (cap_rows + R - 1) / R;
     int slot = 0;
     for (int g = 0; g < ngroups; ++g) {
       Group& gr = plan.groups[g];
       gr.slot0 = slot;
       gr.nslot = 0;
+      if (fixed) {
+        gr.nslot = c->Q * nch_cap;
+        slot += gr.nslot;
+      }
       for (int q = 0; q < c->Q; ++q) {
         const int kg = group_rows(T, gr, q);
         if (kg <= 2) continue;  // partitions 0 and 1 are done by the heads
         const int rows = kg - 2;
         const int nch = (rows + R - 1) / R;
         for (int ch = 0; ch < nch; ++ch) {
-          const int p0 = 2 + (int)((int64_t)ch * rows / nch);
-          const int p1 = 2 + (int)((int64_t)(ch + 1) * rows / nch);
+          const int p0 = fixed ? 2 + ch * R : 2 + (int)((int64_t)ch * rows / nch);
+          const int p1 = fixed ? std::min(kg, 2 + (ch + 1) * R) : 2 + (int)((int64_t)(ch + 1) * rows / nch);
+          const int it_slot = fixed ? gr.slot0 + q * nch_cap + ch : slot;
           for (int sl = 0; sl < nslice; ++sl) {
             Item it{};
             it.kind = K_MAC;
@@ -394,11 +457,13 @@ int build_plan(rta_ctx* c, Plan& plan) {
             it.p0 = p0;
             it.p1 = p1;
             it.k0 = sl * W;
-            it.slot = slot;
+            it.slot = it_slot;
             tier0.push_back(it);
           }
-          ++slot;
-          ++gr.nslot;
+          if (!fixed) {
+            ++slot;
+            ++gr.nslot;
+          }
         }
       }
     }
@@ -414,30 +479,45 @@ int build_plan(rta_ctx* c, Plan& plan) {
     const int nmac = tier_nmac(c, t);
     if (nmac < 1) return RTA_E_STATE;
     const int R = std::max(1, c->tier_rows);
-    struct Chunk { int g, q, p0, p1, slot; };
+    struct Chunk { int g, q, p0, p1, slot, cap; };
     std::vector<Chunk> chunks;
+    const int nch_cap = fixed ? (T.kcap + R - 1) / R : 0;
     int slot = 0;
     for (int g = 0; g < ngroups; ++g) {
       const Group& gr = plan.groups[g];
       plan.tier_slot0[(size_t)t * ngroups + g] = slot;
+      const int gslot0 = slot;
+      if (fixed) slot += c->Q * nch_cap;
       for (int q = 0; q < c->Q; ++q) {
         const int kg = group_rows(T, gr, q);
         if (kg == 0) continue;
         const int nch = (kg + R - 1) / R;
-        for (int ch = 0; ch < nch; ++ch)
-          chunks.push_back(Chunk{g, q, (int)((int64_t)ch * kg / nch),
-                                 (int)((int64_t)(ch + 1) * kg / nch), slot++});
+        for (int ch = 0; ch < nch; ++ch) {
+          if (fixed)
+            chunks.push_back(Chunk{g, q, ch * R, std::min(kg, (ch + 1) * R), gslot0 + q * nch_cap + ch,
+                                   (g * c->Q + q) * nch_cap + ch});
+          else
+            chunks.push_back(Chunk{g, q, (int)((int64_t)ch * kg / nch),
+                                   (int)((int64_t)(ch + 1) * kg / nch), slot++, 0});
+        }
       }
       plan.tier_nslot[(size_t)t * ngroups + g] = slot - plan.tier_slot0[(size_t)t * ngroups + g];
     }
     T.nslots = slot;
-    // spread the chunks over the nmac blocks, balancing rows
+    // spread the chunks over the nmac blocks, balancing rows; with the fixed
+    // serving layout a chunk's block depends on its slot alone, so a frame
+    // whose accumulation straddles a work-list switch still writes every
+    // slot exactly once
     int64_t total = 0;
     for (const Chunk& ch : chunks) total += ch.p1 - ch.p0;
     std::vector<int> when(chunks.size(), 0);
     int64_t acc = 0;
+    const int64_t ncap = (int64_t)ngroups * c->Q * nch_cap;
     for (size_t i = 0; i < chunks.size(); ++i) {
-      when[i] = total > 0 ? (int)std::min<int64_t>(nmac - 1, acc * nmac / total) : 0;
+      if (fixed)
+        when[i] = (int)std::min<int64_t>(nmac - 1, (int64_t)chunks[i].cap * nmac / std::max<int64_t>(1, ncap));
+      else
+        when[i] = total > 0 ? (int)std::min<int64_t>(nmac - 1, acc * nmac / total) : 0;
       acc += chunks[i].p1 - chunks[i].p0;
     }
     for (int ph0 = r - 1; ph0 < n_phase; ph0 += r) {  // phases in which a frame completes
@@ -470,6 +550,7 @@ int build_plan(rta_ctx* c, Plan& plan) {
       }
       for (int g = 0; g < ngroups; ++g) {
         if (plan.tier_nslot[(size_t)t * ngroups + g] == 0) continue;
+        if (fixed && chunks.empty()) continue;  // no source present
         Item it{};
         it.kind = K_FINAL;
         it.tier = t;
@@ -576,16 +657,90 @@ KArgs make_args(const rta_ctx* c, const float* in, float* out, int64_t n) {
   a.tier_nslot = c->tier_nslot;
   a.max_tier_items = c->max_tier_items;
   a.n_groups_total = c->n_groups;
+  a.live = c->live;
   return a;
+}
+
+// Make buffer d the one launches read.
+void activate(rta_ctx* c, const PlanDev& d) {
+  c->items = d.items;
+  c->phase_count = d.phase_count;
+  c->tier_items = d.tier_items;
+  c->tier_count = d.tier_count;
+  c->tier_count_host = d.tier_count_host;
+  for (int t = 0; t < c->n_tiers; ++t) {
+    c->tier[t].pair_row = d.pair_row[t];
+    c->tier[t].pair_K = d.pair_K[t];
+  }
+  c->live = d.live;
+  c->grid_items = d.grid_items;
+  c->h_bytes = d.hb;
+  c->x_bytes = d.xb;
+  c->cmacs = d.cm;
+  c->tail_bytes = d.tb;
+}
+
+int64_t floor_div(int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+// Serving: first block from which a slot whose input stopped at block m owns
+// only zeros -- its delay lines of every tier, input history and partial
+// sums -- so its work items can be dropped and its rows reused.  Tier t's
+// frames f <= f_last see input before m; frame f_last + K_t is the first
+// whose delay line is all zero, and its slots are rewritten (with zeros) by
+// the time its final step has run.
+int64_t drain_end(const rta_ctx* c, int64_t m) {
+  int64_t end = m;
+  for (int t = 0; t < c->n_tiers; ++t) {
+    const TierHost& T = c->tier[t];
+    const int64_t P = T.P, r = T.P / c->B;
+    const int64_t fl = floor_div(m * c->B - 1, P) + 1;
+    const int64_t e = t == 0 ? fl + T.K + 1 : (fl + T.K + 1) * r + tier_nmac(c, t);
+    end = std::max(end, e + 1);
+  }
+  return end;
+}
+
+// Serving: at a block boundary, switch to a newer work list and advance the
+// slot states (block thread; short critical section).
+int serve_boundary(rta_ctx* c, hipStream_t s) {
+  Serve* sv = c->serve;
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (sv->pending) {
+    // launches so far used the old buffer; this event passes once they are
+    // done, after which a control call may overwrite it
+    HIP_TRY(c, hipEventRecord(sv->retire[sv->active], s));
+    sv->retire_valid[sv->active] = true;
+    sv->active ^= 1;
+    sv->pending = false;
+    ++sv->swaps;
+    activate(c, sv->dev[sv->active]);
+    for (ServeSlot& sl : sv->slots) {
+      if (sl.state == RTA_SLOT_JOINING) {
+        sl.state = RTA_SLOT_LIVE;
+        sl.start = c->block;
+      } else if (sl.state == RTA_SLOT_LEAVING) {
+        sl.state = RTA_SLOT_DRAINING;
+        sl.stop = c->block;
+        sl.free_at = drain_end(c, c->block);
+      }
+    }
+  }
+  for (ServeSlot& sl : sv->slots)
+    if (sl.state == RTA_SLOT_DRAINING && c->block >= sl.free_at) sl.state = RTA_SLOT_FREE;
+  return RTA_OK;
 }
 
 // One block: heads of block n and tails of block n + 1 in a single launch,
 // then, in blocks with later-tier FFTs or finals, one k_tier launch.
 // `flag`: raise the host-visible completion flag (rta_process).
 int launch_block(rta_ctx* c, const float* in, float* out, hipStream_t s, bool flag = false) {
+  if (c->serve != nullptr) {
+    const int st = serve_boundary(c, s);
+    if (st != RTA_OK) return st;
+  }
   KArgs a = make_args(c, in, out, c->block);
   if (flag) a.done_flag = c->m_flag;
-  const unsigned grid = (unsigned)(c->head_slots + c->max_items);
+  const unsigned grid = (unsigned)(c->head_slots + c->grid_items);
   const int phase = (int)(c->block % c->n_phase);
   const int n_tier = c->tier_count_host.empty() ? 0 : c->tier_count_host[phase];
   hipEvent_t* e = nullptr;
@@ -653,73 +808,191 @@ struct TmpDev {
   }
 };
 
-int build_spectra(rta_ctx* c, const float* const* filters, const int64_t* lengths) {
-  int64_t max_len = 0;
-  for (int64_t i = 0; i < (int64_t)c->Q * c->L; ++i) max_len = std::max(max_len, lengths[i]);
-  const int64_t stage_floats = std::max<int64_t>(max_len, kStageBytes / 4);
-  TmpDev stage, drows, drange;
-  if (hipMalloc(&stage.p, sizeof(float) * (size_t)stage_floats) != hipSuccess ||
-      hipMalloc(&drange.p, sizeof(int)) != hipSuccess) {
-    (void)hipGetLastError();
-    return RTA_E_NOMEM;
-  }
-  HIP_TRY(c, hipMemsetAsync(drange.p, 0, sizeof(int), c->stream));
+// One filter's partitions in one tier: taps [o_t, o_t + kp P_t) of `taps`
+// (len taps in all) go to spectra rows [row, row + kp).
+struct SpecJob {
+  int tier;
+  const float* taps;
+  int64_t len, row;
+  int kp;
+};
 
+// Build the spectra rows of `jobs` on stream s through the given device
+// staging buffers (d_stage: stage_floats taps, at least one whole filter;
+// d_rows: row_cap rows, at least stage_floats / P_0 + jobs per tier).
+// Synchronous; RTA_E_RANGE when an FP16 spectrum value overflows.
+int run_spectra(rta_ctx* c, const std::vector<SpecJob>& jobs, hipStream_t s, float* d_stage,
+                int64_t stage_floats, SpecRow* d_rows, int64_t row_cap, int* d_range) {
+  HIP_TRY(c, hipMemsetAsync(d_range, 0, sizeof(int), s));
   for (int t = 0; t < c->n_tiers; ++t) {
     TierHost& T = c->tier[t];
     const int P = T.P;
     const size_t lds = sizeof(float2) * 2 * (size_t)P;
-    // a batch holds at most stage_floats taps, hence at most this many rows
-    const int64_t row_cap = stage_floats / P + (int64_t)c->Q * c->L + 1;
-    if (drows.p) { (void)hipFree(drows.p); drows.p = nullptr; }
-    if (hipMalloc(&drows.p, sizeof(SpecRow) * (size_t)row_cap) != hipSuccess) {
-      (void)hipGetLastError();
-      return RTA_E_NOMEM;
-    }
     std::vector<SpecRow> rows;
     std::vector<float> host_stage;
     auto flush = [&]() -> int {
       if (rows.empty()) return RTA_OK;
-      HIP_TRY(c, hipMemcpyAsync(stage.p, host_stage.data(), sizeof(float) * host_stage.size(),
-                                hipMemcpyHostToDevice, c->stream));
-      HIP_TRY(c, hipMemcpyAsync(drows.p, rows.data(), sizeof(SpecRow) * rows.size(),
-                                hipMemcpyHostToDevice, c->stream));
-      HIP_TRY(c, launch_spectra(c->dtype, dim3((unsigned)rows.size()), lds, c->stream,
-                                static_cast<const float*>(stage.p),
-                                static_cast<const SpecRow*>(drows.p), T.H, P, T.logP, T.tw,
-                                static_cast<int*>(drange.p)));
-      HIP_TRY(c, hipStreamSynchronize(c->stream));
+      HIP_TRY(c, hipMemcpyAsync(d_stage, host_stage.data(), sizeof(float) * host_stage.size(),
+                                hipMemcpyHostToDevice, s));
+      HIP_TRY(c, hipMemcpyAsync(d_rows, rows.data(), sizeof(SpecRow) * rows.size(),
+                                hipMemcpyHostToDevice, s));
+      HIP_TRY(c, launch_spectra(c->dtype, dim3((unsigned)rows.size()), lds, s, d_stage, d_rows, T.H,
+                                P, T.logP, T.tw, d_range));
+      HIP_TRY(c, hipStreamSynchronize(s));
       rows.clear();
       host_stage.clear();
       return RTA_OK;
     };
     int st;
+    for (const SpecJob& j : jobs) {
+      if (j.tier != t || j.kp == 0) continue;
+      const int64_t a0 = T.offset, a1 = std::min(j.len, T.offset + (int64_t)j.kp * P);
+      const int64_t n = std::max<int64_t>(0, a1 - a0);
+      if (n > stage_floats || j.kp > row_cap) return RTA_E_STATE;
+      if ((int64_t)host_stage.size() + n > stage_floats || (int64_t)rows.size() + j.kp > row_cap)
+        if ((st = flush()) != RTA_OK) return st;
+      const int64_t base = (int64_t)host_stage.size();
+      if (n > 0) host_stage.insert(host_stage.end(), j.taps + a0, j.taps + a1);
+      for (int p = 0; p < j.kp; ++p) {
+        SpecRow r{};
+        r.src = base + (int64_t)p * P;
+        r.len = (int32_t)std::max<int64_t>(0, std::min<int64_t>(P, n - (int64_t)p * P));
+        r.dst = j.row + p;
+        rows.push_back(r);
+      }
+    }
+    if ((st = flush()) != RTA_OK) return st;
+  }
+  int range = 0;
+  HIP_TRY(c, hipMemcpyAsync(&range, d_range, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  return range ? RTA_E_RANGE : RTA_OK;
+}
+
+int build_spectra(rta_ctx* c, const float* const* filters, const int64_t* lengths) {
+  int64_t max_len = 0;
+  for (int64_t i = 0; i < (int64_t)c->Q * c->L; ++i) max_len = std::max(max_len, lengths[i]);
+  const int64_t stage_floats = std::max<int64_t>(max_len, kStageBytes / 4);
+  // a batch holds at most stage_floats taps, hence at most this many rows
+  const int64_t row_cap = stage_floats / c->tier[0].P + (int64_t)c->Q * c->L + 1;
+  TmpDev stage, drows, drange;
+  if (hipMalloc(&stage.p, sizeof(float) * (size_t)stage_floats) != hipSuccess ||
+      hipMalloc(&drows.p, sizeof(SpecRow) * (size_t)row_cap) != hipSuccess ||
+      hipMalloc(&drange.p, sizeof(int)) != hipSuccess) {
+    (void)hipGetLastError();
+    return RTA_E_NOMEM;
+  }
+  std::vector<SpecJob> jobs;
+  for (int t = 0; t < c->n_tiers; ++t) {
+    const TierHost& T = c->tier[t];
     for (int l = 0; l < c->L; ++l)
       for (int q = 0; q < c->Q; ++q) {
         const int pair_in = q * c->L + l;  // caller layout [in][out]
         const int pair = l * c->Q + q;     // device layout [out][in]
-        const int kp = T.kp[pair];
-        if (kp == 0) continue;
-        const int64_t len = lengths[pair_in];
-        const int64_t a0 = T.offset, a1 = std::min(len, T.offset + (int64_t)kp * P);
-        const int64_t n = a1 - a0;
-        if ((int64_t)host_stage.size() + n > stage_floats || (int64_t)rows.size() + kp > row_cap)
-          if ((st = flush()) != RTA_OK) return st;
-        const int64_t base = (int64_t)host_stage.size();
-        host_stage.insert(host_stage.end(), filters[pair_in] + a0, filters[pair_in] + a1);
-        for (int p = 0; p < kp; ++p) {
-          SpecRow r{};
-          r.src = base + (int64_t)p * P;
-          r.len = (int32_t)std::max<int64_t>(0, std::min<int64_t>(P, n - (int64_t)p * P));
-          r.dst = T.row[pair] + p;
-          rows.push_back(r);
-        }
+        if (T.kp[pair] == 0) continue;
+        jobs.push_back(SpecJob{t, filters[pair_in], lengths[pair_in], T.row[pair], T.kp[pair]});
       }
-    if ((st = flush()) != RTA_OK) return st;
   }
-  int range = 0;
-  HIP_TRY(c, hipMemcpy(&range, drange.p, sizeof(int), hipMemcpyDeviceToHost));
-  return range ? RTA_E_RANGE : RTA_OK;
+  return run_spectra(c, jobs, c->stream, static_cast<float*>(stage.p), stage_floats,
+                     static_cast<SpecRow*>(drows.p), row_cap, static_cast<int*>(drange.p));
+}
+
+// ---------------------------------------------------------------------------
+// Serving: work-list buffers.
+// ---------------------------------------------------------------------------
+
+// Copy `plan`, the pair tables in c->tier[].row/kp and the live mask into
+// buffer d on stream s (synchronous).  Lists longer than the buffers' stride
+// (the stride is the longest list of the every-slot-present plan) lose their
+// XCD padding instead; the items are a subset of that plan's, so they fit.
+int upload_plan(rta_ctx* c, const Plan& plan, PlanDev& d, const std::vector<int32_t>& live,
+                hipStream_t s) {
+  const size_t mb = (size_t)c->max_items, mt = (size_t)c->max_tier_items;
+  std::vector<Item> all_b((size_t)c->n_phase * mb, Item{}), all_t((size_t)c->n_phase * mt, Item{});
+  std::vector<int32_t> cnt_b(c->n_phase), cnt_t(c->n_phase);
+  for (auto& it : all_b) it.kind = K_NOP;
+  for (auto& it : all_t) it.kind = K_NOP;
+  int grid = 0;
+  for (int ph = 0; ph < c->n_phase; ++ph) {
+    std::vector<Item> lst = plan.block[ph];
+    if (lst.size() > mb) {
+      lst.erase(std::remove_if(lst.begin(), lst.end(), [](const Item& it) { return it.kind == K_NOP; }),
+                lst.end());
+      if (lst.size() > mb) return RTA_E_STATE;
+    }
+    if (plan.tier[ph].size() > mt) return RTA_E_STATE;
+    std::copy(lst.begin(), lst.end(), all_b.begin() + (size_t)ph * mb);
+    std::copy(plan.tier[ph].begin(), plan.tier[ph].end(), all_t.begin() + (size_t)ph * mt);
+    cnt_b[ph] = (int32_t)lst.size();
+    cnt_t[ph] = (int32_t)plan.tier[ph].size();
+    grid = std::max(grid, cnt_b[ph]);
+  }
+  HIP_TRY(c, hipMemcpyAsync(d.items, all_b.data(), sizeof(Item) * all_b.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(c, hipMemcpyAsync(d.phase_count, cnt_b.data(), sizeof(int32_t) * cnt_b.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(c, hipMemcpyAsync(d.tier_items, all_t.data(), sizeof(Item) * all_t.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(c, hipMemcpyAsync(d.tier_count, cnt_t.data(), sizeof(int32_t) * cnt_t.size(), hipMemcpyHostToDevice, s));
+  for (int t = 0; t < c->n_tiers; ++t) {
+    const TierHost& T = c->tier[t];
+    HIP_TRY(c, hipMemcpyAsync(d.pair_row[t], T.row.data(), sizeof(int64_t) * T.row.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(d.pair_K[t], T.kp.data(), sizeof(int32_t) * T.kp.size(), hipMemcpyHostToDevice, s));
+  }
+  HIP_TRY(c, hipMemcpyAsync(d.live, live.data(), sizeof(int32_t) * live.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  d.tier_count_host = cnt_t;
+  d.grid_items = grid;
+  return RTA_OK;
+}
+
+// Work lists of a new serving context: buffers sized by the plan with every
+// slot present at max_taps, and the empty plan in buffer 0.
+int serve_lists(rta_ctx* c, Plan& plan) {
+  Serve* sv = c->serve;
+  int st;
+  for (int t = 0; t < c->n_tiers; ++t) std::fill(c->tier[t].kp.begin(), c->tier[t].kp.end(), c->tier[t].kcap);
+  Plan cap;
+  if ((st = build_plan(c, cap)) != RTA_OK) return st;
+  for (int t = 0; t < c->n_tiers; ++t) std::fill(c->tier[t].kp.begin(), c->tier[t].kp.end(), 0);
+  if ((st = build_plan(c, plan)) != RTA_OK) return st;
+  // the slot layout must not depend on which sources are present
+  if (cap.tier_slot0 != plan.tier_slot0 || cap.tier_nslot != plan.tier_nslot ||
+      cap.groups.size() != plan.groups.size())
+    return RTA_E_STATE;
+  for (size_t g = 0; g < cap.groups.size(); ++g)
+    if (cap.groups[g].slot0 != plan.groups[g].slot0 || cap.groups[g].nslot != plan.groups[g].nslot)
+      return RTA_E_STATE;
+  c->n_groups = (int)plan.groups.size();
+  c->head_slots = (c->n_groups + kXcds - 1) / kXcds * kXcds;
+  size_t mb = 1, mt = 1;
+  for (int ph = 0; ph < c->n_phase; ++ph) {
+    mb = std::max(mb, cap.block[ph].size());
+    mt = std::max(mt, cap.tier[ph].size());
+  }
+  c->max_items = (int)mb;
+  c->max_tier_items = (int)mt;
+  for (PlanDev& d : sv->dev) {
+    if ((st = dev_alloc(c, &d.items, (size_t)c->n_phase * mb)) != RTA_OK) return st;
+    if ((st = dev_alloc(c, &d.phase_count, (size_t)c->n_phase)) != RTA_OK) return st;
+    if ((st = dev_alloc(c, &d.tier_items, (size_t)c->n_phase * mt)) != RTA_OK) return st;
+    if ((st = dev_alloc(c, &d.tier_count, (size_t)c->n_phase)) != RTA_OK) return st;
+    for (int t = 0; t < c->n_tiers; ++t) {
+      if ((st = dev_alloc(c, &d.pair_row[t], c->tier[t].row.size())) != RTA_OK) return st;
+      if ((st = dev_alloc(c, &d.pair_K[t], c->tier[t].kp.size())) != RTA_OK) return st;
+    }
+    if ((st = dev_alloc(c, &d.live, (size_t)c->Q)) != RTA_OK) return st;
+  }
+  const std::vector<int32_t> live((size_t)c->Q, 0);
+  if ((st = upload_plan(c, plan, sv->dev[0], live, c->stream)) != RTA_OK) return st;
+  sv->active = 0;
+  activate(c, sv->dev[0]);
+  // admissions: staging for one source's taps and spectrum rows
+  sv->stage_floats = std::max<int64_t>(sv->cfg.max_taps, kStageBytes / 4);
+  sv->row_cap = sv->stage_floats / c->tier[0].P + c->L + 1;
+  if ((st = dev_alloc(c, &sv->d_stage, (size_t)sv->stage_floats)) != RTA_OK) return st;
+  if ((st = dev_alloc(c, &sv->d_rows, (size_t)sv->row_cap)) != RTA_OK) return st;
+  if ((st = dev_alloc(c, &sv->d_range, 1)) != RTA_OK) return st;
+  HIP_TRY(c, hipStreamCreateWithFlags(&sv->aux, hipStreamNonBlocking));
+  for (hipEvent_t& e : sv->retire) HIP_TRY(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  return RTA_OK;
 }
 
 int create_impl(rta_ctx* c, const std::vector<int>& size, const std::vector<int>& count,
@@ -727,6 +1000,24 @@ int create_impl(rta_ctx* c, const std::vector<int>& size, const std::vector<int>
   int st;
   HIP_TRY(c, hipGetDevice(&c->device));
   HIP_TRY(c, hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+
+  // serving: the arena holds `scale` of the spectra of every slot at
+  // max_taps on every output (the lengths passed here), at least one filter
+  // per tier
+  Serve* sv = c->serve;
+  const size_t eb = spectra_elem_bytes(c->dtype);
+  double scale = 1.0;
+  if (sv != nullptr && sv->cfg.arena_bytes > 0) {
+    double full = 0;
+    int64_t o = 0;
+    for (size_t t = 0; t < size.size(); ++t) {
+      const int64_t kc = std::min<int64_t>(count[t] > 0 ? count[t] : INT32_MAX,
+                                           std::max<int64_t>(0, (sv->cfg.max_taps - o + size[t] - 1) / size[t]));
+      full += (double)c->Q * c->L * kc * size[t] * eb;
+      o += (count[t] > 0 ? count[t] : kc) * (int64_t)size[t];
+    }
+    scale = std::min(1.0, (double)sv->cfg.arena_bytes / std::max(1.0, full));
+  }
 
   // tiers and partition counts
   c->n_tiers = (int)size.size();
@@ -746,17 +1037,24 @@ int create_impl(rta_ctx* c, const std::vector<int>& size, const std::vector<int>
         int64_t need = len > off ? (len - off + T.P - 1) / T.P : 0;
         if (count[t] > 0) need = std::min<int64_t>(need, count[t]);
         const int pair = l * c->Q + q;
+        kmax = std::max<int>(kmax, (int)need);
+        if (sv != nullptr) continue;  // no source yet
         T.kp[pair] = (int)need;
         if (need > 0) {
           T.row[pair] = rows;
           rows += need;
         }
-        kmax = std::max<int>(kmax, (int)need);
       }
     T.count = count[t] > 0 ? count[t] : kmax;
     T.K = std::max(1, kmax);
     off += (int64_t)T.count * T.P;
-    const size_t eb = spectra_elem_bytes(c->dtype);
+    if (sv != nullptr) {
+      T.kcap = kmax;
+      const int64_t full = (int64_t)c->Q * c->L * kmax;
+      rows = std::max<int64_t>(kmax, (int64_t)std::floor(scale * (double)full));
+      rows = std::min(rows, full);
+      sv->arena[t].reset(rows);
+    }
     const double per_block = (double)c->B / T.P;  // a tier's frame recurs every P/B blocks
     c->spectra_bytes += rows * T.P * (int64_t)eb;
     c->h_bytes += (double)rows * T.P * eb * per_block;
@@ -778,6 +1076,7 @@ int create_impl(rta_ctx* c, const std::vector<int>& size, const std::vector<int>
     const std::vector<float2> tw = twiddles(T.P);
     HIP_TRY(c, hipMemcpy(T.tw, tw.data(), sizeof(float2) * tw.size(), hipMemcpyHostToDevice));
   }
+  if (sv != nullptr) c->h_bytes = c->x_bytes = c->cmacs = c->tail_bytes = 0;  // per list
   c->io_bytes = 4.0 * c->B * (c->Q + c->L);
   c->hist_len = std::max<int64_t>(2 * c->B, 2 * (int64_t)c->tier[c->n_tiers - 1].P);
   c->hist_len = int64_t(1) << ilog2(c->hist_len);
@@ -788,9 +1087,9 @@ int create_impl(rta_ctx* c, const std::vector<int>& size, const std::vector<int>
   for (int t = 1; t < c->n_tiers; ++t)
     if ((st = dev_alloc(c, &c->tier[t].oring, (size_t)c->L * c->ring_len)) != RTA_OK) return st;
 
-  // spectra, then the heads' dense copy of partitions 0 and 1
-  if ((st = build_spectra(c, filters, lengths)) != RTA_OK) return st;
-  const size_t eb = spectra_elem_bytes(c->dtype);
+  // spectra, then the heads' dense copy of partitions 0 and 1 (serving: no
+  // source yet, so the copy starts as zeros)
+  if (sv == nullptr && (st = build_spectra(c, filters, lengths)) != RTA_OK) return st;
   if ((st = dev_alloc(c, reinterpret_cast<char**>(&c->H01), (size_t)c->L * c->Q * 2 * c->tier[0].P * eb)) != RTA_OK)
     return st;
   HIP_TRY(c, launch_gather(c->dtype, c->tier[0], c->L * c->Q, c->H01, c->stream));
@@ -804,6 +1103,9 @@ int create_impl(rta_ctx* c, const std::vector<int>& size, const std::vector<int>
 
   // work lists
   Plan plan;
+  if (sv != nullptr) {
+    if ((st = serve_lists(c, plan)) != RTA_OK) return st;
+  } else {
   if ((st = build_plan(c, plan)) != RTA_OK) return st;
   c->n_groups = (int)plan.groups.size();
   c->head_slots = (c->n_groups + kXcds - 1) / kXcds * kXcds;  // keeps tails' XCD residues
@@ -830,14 +1132,16 @@ int create_impl(rta_ctx* c, const std::vector<int>& size, const std::vector<int>
   if ((st = dev_alloc(c, &c->phase_count, cnt_b.size())) != RTA_OK) return st;
   if ((st = dev_alloc(c, &c->tier_items, all_t.size())) != RTA_OK) return st;
   if ((st = dev_alloc(c, &c->tier_count, cnt_t.size())) != RTA_OK) return st;
-  if ((st = dev_alloc(c, &c->tier_slot0, plan.tier_slot0.size())) != RTA_OK) return st;
-  if ((st = dev_alloc(c, &c->tier_nslot, plan.tier_nslot.size())) != RTA_OK) return st;
-  if ((st = dev_alloc(c, &c->groups, plan.groups.size())) != RTA_OK) return st;
-  if ((st = dev_alloc(c, &c->head_count, 1)) != RTA_OK) return st;
   HIP_TRY(c, hipMemcpy(c->items, all_b.data(), sizeof(Item) * all_b.size(), hipMemcpyHostToDevice));
   HIP_TRY(c, hipMemcpy(c->phase_count, cnt_b.data(), sizeof(int32_t) * cnt_b.size(), hipMemcpyHostToDevice));
   HIP_TRY(c, hipMemcpy(c->tier_items, all_t.data(), sizeof(Item) * all_t.size(), hipMemcpyHostToDevice));
   HIP_TRY(c, hipMemcpy(c->tier_count, cnt_t.data(), sizeof(int32_t) * cnt_t.size(), hipMemcpyHostToDevice));
+  c->grid_items = c->max_items;
+  }
+  if ((st = dev_alloc(c, &c->tier_slot0, plan.tier_slot0.size())) != RTA_OK) return st;
+  if ((st = dev_alloc(c, &c->tier_nslot, plan.tier_nslot.size())) != RTA_OK) return st;
+  if ((st = dev_alloc(c, &c->groups, plan.groups.size())) != RTA_OK) return st;
+  if ((st = dev_alloc(c, &c->head_count, 1)) != RTA_OK) return st;
   HIP_TRY(c, hipMemcpy(c->tier_slot0, plan.tier_slot0.data(), sizeof(int32_t) * plan.tier_slot0.size(), hipMemcpyHostToDevice));
   HIP_TRY(c, hipMemcpy(c->tier_nslot, plan.tier_nslot.data(), sizeof(int32_t) * plan.tier_nslot.size(), hipMemcpyHostToDevice));
   HIP_TRY(c, hipMemcpy(c->groups, plan.groups.data(), sizeof(Group) * plan.groups.size(), hipMemcpyHostToDevice));
@@ -898,6 +1202,16 @@ void free_all(rta_ctx* c) {
   }
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
   c->events.clear();
+  if (c->serve) {
+    if (c->serve->aux) {
+      (void)hipStreamSynchronize(c->serve->aux);
+      (void)hipStreamDestroy(c->serve->aux);
+    }
+    for (hipEvent_t e : c->serve->retire)
+      if (e) (void)hipEventDestroy(e);
+    delete c->serve;
+    c->serve = nullptr;
+  }
   for (void* p : c->dev_allocs) (void)hipFree(p);
   c->dev_allocs.clear();
   if (c->h_in) (void)hipHostFree(c->h_in);
@@ -966,25 +1280,280 @@ int time_blocks(rta_ctx* c, int blocks, double* us) {
   return st;
 }
 
-}  // namespace
+// ---------------------------------------------------------------------------
+// Serving: control calls (hold sv->ctl).
+// ---------------------------------------------------------------------------
 
-extern "C" {
+bool present(int state) { return state != RTA_SLOT_FREE; }
 
-int rta_create_tuned(rta_ctx** out, double fs, int32_t block, const rta_scheme* scheme,
-                     int32_t n_in, int32_t n_out, const float* const* filters,
-                     const int64_t* lengths, int32_t spectra, uint32_t flags,
-                     const rta_tuning* tuning) {
-  if (out == nullptr) return RTA_E_ARG;
-  *out = nullptr;
-  std::vector<int> size, count;
-  int st = validate(fs, block, scheme, n_in, n_out, filters, lengths, spectra, flags, size, count);
-  if (st != RTA_OK) return st;
-  if (tuning != nullptr) {
-    const int g = tuning->outputs_per_group;
-    if ((g != 0 && g != 1 && g != 2 && g != 4) || tuning->tail_items < 0 || tuning->tail_rows < 0 ||
-        tuning->tier_rows < 0)
-      return RTA_E_ARG;
+// Return the arena rows of slots that have become free.
+void reclaim(Serve* sv, int n_tiers) {
+  std::vector<int> freed;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    for (size_t q = 0; q < sv->slots.size(); ++q)
+      if (sv->slots[q].state == RTA_SLOT_FREE && sv->slots[q].rows_held) freed.push_back((int)q);
   }
+  for (int q : freed) {
+    ServeSlot& sl = sv->slots[q];
+    for (int t = 0; t < n_tiers; ++t) {
+      for (size_t l = 0; l < sl.row[t].size(); ++l)
+        if (sl.row[t][l] >= 0) sv->arena[t].release(sl.row[t][l], sl.kp[t][l]);
+      sl.row[t].clear();
+      sl.kp[t].clear();
+    }
+    sl.rows_held = false;
+  }
+}
+
+// Build the work list for the slot states `states` (one slot may be given a
+// state it will take when the list is published), write it into the
+// buffer launches are not reading, and publish it: the next block switches
+// to it.  `after` is applied to the slot states in the same critical section
+// that publishes the list.  gather: refresh the heads' copy of partitions 0
+// and 1 from the new pair tables first.
+template <typename F>
+int commit_plan(rta_ctx* c, std::vector<int> states, bool gather, F after) {
+  Serve* sv = c->serve;
+  const int Q = c->Q, L = c->L;
+  int st;
+  PlanDev tmp;  // per-block figures of the new list
+  for (int t = 0; t < c->n_tiers; ++t) {
+    TierHost& T = c->tier[t];
+    std::fill(T.row.begin(), T.row.end(), -1);
+    std::fill(T.kp.begin(), T.kp.end(), 0);
+  }
+  std::vector<int32_t> live((size_t)Q, 0);
+  for (int q = 0; q < Q; ++q) {
+    if (!present(states[q])) continue;
+    const ServeSlot& sl = sv->slots[q];
+    live[q] = (states[q] == RTA_SLOT_JOINING || states[q] == RTA_SLOT_LIVE) ? 1 : 0;
+    for (int t = 0; t < c->n_tiers; ++t)
+      for (int l = 0; l < L; ++l) {
+        c->tier[t].row[(size_t)l * Q + q] = sl.row[t][l];
+        c->tier[t].kp[(size_t)l * Q + q] = sl.kp[t][l];
+      }
+    tmp.hb += sl.hb;
+    tmp.xb += sl.xb;
+    tmp.cm += sl.cm;
+  }
+  {
+    const TierHost& T = c->tier[0];
+    const size_t ebytes = spectra_elem_bytes(c->dtype);
+    double tail_rows = 0;
+    std::vector<int> kq((size_t)Q, 0);
+    for (int l = 0; l < L; ++l)
+      for (int q = 0; q < Q; ++q) {
+        const int kp = T.kp[(size_t)l * Q + q];
+        tail_rows += std::max(0, kp - 2);
+        kq[q] = std::max(kq[q], kp);
+      }
+    double xr = 0;
+    for (int k : kq) xr += std::max(0, k - 2);
+    tmp.tb = tail_rows * T.P * ebytes + xr * T.P * 8.0;
+  }
+  Plan plan;
+  if ((st = build_plan(c, plan)) != RTA_OK) return st;
+
+  int target;
+  bool wait = false;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    target = sv->active ^ 1;
+    if (sv->pending)
+      sv->pending = false;  // the other buffer was published but not yet read
+    else
+      wait = sv->retire_valid[target];
+  }
+  if (wait) HIP_TRY(c, hipEventSynchronize(sv->retire[target]));
+  PlanDev& d = sv->dev[target];
+  if ((st = upload_plan(c, plan, d, live, sv->aux)) != RTA_OK) return st;
+  if (gather) {
+    TierHost T0 = c->tier[0];
+    T0.pair_row = d.pair_row[0];
+    T0.pair_K = d.pair_K[0];
+    HIP_TRY(c, launch_gather(c->dtype, T0, L * Q, c->H01, sv->aux));
+    HIP_TRY(c, hipStreamSynchronize(sv->aux));
+  }
+  d.hb = tmp.hb;
+  d.xb = tmp.xb;
+  d.cm = tmp.cm;
+  d.tb = tmp.tb;
+  std::lock_guard<std::mutex> lk(sv->mu);
+  after();
+  sv->pending = true;
+  return RTA_OK;
+}
+
+std::vector<int> slot_states(Serve* sv) {
+  std::lock_guard<std::mutex> lk(sv->mu);
+  std::vector<int> st;
+  for (const ServeSlot& sl : sv->slots) st.push_back(sl.state);
+  return st;
+}
+
+int serve_admit(rta_ctx* c, const float* const* filters, const int64_t* lengths, int32_t* slot) {
+  Serve* sv = c->serve;
+  const int L = c->L;
+  std::lock_guard<std::mutex> cl(sv->ctl);
+  if (c->poisoned) return RTA_E_DEVICE;
+  reclaim(sv, c->n_tiers);
+
+  // partitions per tier of each of the source's filters, and what it streams
+  const size_t eb = spectra_elem_bytes(c->dtype);
+  ServeSlot src;
+  for (int l = 0; l < L; ++l) src.taps = std::max(src.taps, lengths[l]);
+  for (int t = 0; t < c->n_tiers; ++t) {
+    const TierHost& T = c->tier[t];
+    const double per_block = (double)c->B / T.P;
+    src.row[t].assign((size_t)L, -1);
+    src.kp[t].assign((size_t)L, 0);
+    int kmax = 0;
+    for (int l = 0; l < L; ++l) {
+      const int64_t len = lengths[l];
+      int64_t need = len > T.offset ? (len - T.offset + T.P - 1) / T.P : 0;
+      need = std::min<int64_t>(need, T.count);
+      src.kp[t][l] = (int)need;
+      kmax = std::max(kmax, (int)need);
+      src.hb += (double)need * T.P * eb * per_block;
+      src.cm += (double)need * T.P * per_block;
+    }
+    src.xb += (double)kmax * T.P * 8.0 * per_block;
+  }
+
+  int q = -1;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    double bytes = 0;
+    for (const ServeSlot& sl : sv->slots)
+      if (present(sl.state)) bytes += sl.hb + sl.xb;
+    for (size_t i = 0; i < sv->slots.size() && q < 0; ++i)
+      if (sv->slots[i].state == RTA_SLOT_FREE && !sv->slots[i].rows_held) q = (int)i;
+    if (q < 0) {
+      ++sv->rej_slots;
+      return RTA_E_CAPACITY;
+    }
+    if (sv->cfg.budget_bytes > 0 && bytes + src.hb + src.xb > sv->cfg.budget_bytes) {
+      ++sv->rej_budget;
+      return RTA_E_CAPACITY;
+    }
+  }
+
+  // arena rows: one contiguous range per (tier, output)
+  auto give_back = [&]() {
+    for (int t = 0; t < c->n_tiers; ++t)
+      for (int l = 0; l < L; ++l)
+        if (src.row[t][l] >= 0) {
+          sv->arena[t].release(src.row[t][l], src.kp[t][l]);
+          src.row[t][l] = -1;
+        }
+  };
+  for (int t = 0; t < c->n_tiers; ++t)
+    for (int l = 0; l < L; ++l) {
+      if (src.kp[t][l] == 0) continue;
+      src.row[t][l] = sv->arena[t].alloc(src.kp[t][l]);
+      if (src.row[t][l] < 0) {
+        give_back();
+        std::lock_guard<std::mutex> lk(sv->mu);
+        ++sv->rej_mem;
+        return RTA_E_NOMEM;
+      }
+    }
+
+  // spectra into those rows (no launch reads them yet)
+  std::vector<SpecJob> jobs;
+  for (int t = 0; t < c->n_tiers; ++t)
+    for (int l = 0; l < L; ++l)
+      if (src.kp[t][l] > 0) jobs.push_back(SpecJob{t, filters[l], lengths[l], src.row[t][l], src.kp[t][l]});
+  int st = run_spectra(c, jobs, sv->aux, sv->d_stage, sv->stage_floats, sv->d_rows, sv->row_cap,
+                       sv->d_range);
+  if (st != RTA_OK) {
+    give_back();
+    return st;
+  }
+
+  ServeSlot& sl = sv->slots[q];  // FREE and without rows: only this call touches it
+  for (int t = 0; t < c->n_tiers; ++t) {
+    sl.row[t] = src.row[t];
+    sl.kp[t] = src.kp[t];
+  }
+  sl.taps = src.taps;
+  sl.hb = src.hb;
+  sl.xb = src.xb;
+  sl.cm = src.cm;
+  sl.rows_held = true;
+  sl.start = sl.stop = sl.free_at = -1;
+  std::vector<int> states = slot_states(sv);
+  states[q] = RTA_SLOT_JOINING;
+  st = commit_plan(c, states, true, [&]() {
+    sv->slots[q].state = RTA_SLOT_JOINING;
+    ++sv->admitted;
+  });
+  if (st != RTA_OK) {
+    give_back();
+    for (int t = 0; t < c->n_tiers; ++t) {
+      sl.row[t].clear();
+      sl.kp[t].clear();
+    }
+    sl.rows_held = false;
+    return st;
+  }
+  *slot = q;
+  return RTA_OK;
+}
+
+int serve_release(rta_ctx* c, int32_t q) {
+  Serve* sv = c->serve;
+  std::lock_guard<std::mutex> cl(sv->ctl);
+  if (c->poisoned) return RTA_E_DEVICE;
+  std::vector<int> states = slot_states(sv);
+  if (states[q] != RTA_SLOT_JOINING && states[q] != RTA_SLOT_LIVE) return RTA_E_STATE;
+  states[q] = RTA_SLOT_LEAVING;
+  return commit_plan(c, states, false, [&]() { sv->slots[q].state = RTA_SLOT_LEAVING; });
+}
+
+// rta_reset for a serving context: the device is idle; zero the state, keep
+// the live sources (live from block 0) and free the released ones.
+int serve_reset(rta_ctx* c) {
+  Serve* sv = c->serve;
+  std::lock_guard<std::mutex> cl(sv->ctl);
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    for (ServeSlot& sl : sv->slots) {
+      if (sl.state == RTA_SLOT_JOINING || sl.state == RTA_SLOT_LIVE) {
+        sl.state = RTA_SLOT_LIVE;
+        sl.start = 0;
+        sl.stop = sl.free_at = -1;
+      } else if (sl.state != RTA_SLOT_FREE) {
+        sl.state = RTA_SLOT_FREE;
+      }
+    }
+  }
+  reclaim(sv, c->n_tiers);
+  // publish a list without the freed slots, then switch to it right away
+  int st = commit_plan(c, slot_states(sv), true, []() {});
+  if (st != RTA_OK) return st;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->active ^= 1;
+    sv->pending = false;
+    sv->retire_valid[0] = sv->retire_valid[1] = false;
+    activate(c, sv->dev[sv->active]);
+  }
+  return zero_state(c);
+}
+
+bool tuning_ok(const rta_tuning* tuning) {
+  if (tuning == nullptr) return true;
+  const int g = tuning->outputs_per_group;
+  return !((g != 0 && g != 1 && g != 2 && g != 4) || tuning->tail_items < 0 || tuning->tail_rows < 0 ||
+           tuning->tier_rows < 0);
+}
+
+int create_ctx(rta_ctx** out, double fs, int32_t block, const std::vector<int>& size,
+               const std::vector<int>& count, int32_t n_in, int32_t n_out,
+               const float* const* filters, const int64_t* lengths, int32_t spectra,
+               uint32_t flags, const rta_tuning* tuning, const rta_serve_config* cfg) {
   rta_ctx* c = new (std::nothrow) rta_ctx();
   if (c == nullptr) return RTA_E_NOMEM;
   c->fs = fs;
@@ -1002,7 +1571,16 @@ int rta_create_tuned(rta_ctx** out, double fs, int32_t block, const rta_scheme* 
     if (tuning->tail_rows) c->rows_per_item = tuning->tail_rows;
     if (tuning->tier_rows) c->tier_rows = tuning->tier_rows;
   }
-  st = create_impl(c, size, count, filters, lengths);
+  if (cfg != nullptr) {
+    c->serve = new (std::nothrow) Serve();
+    if (c->serve == nullptr) {
+      delete c;
+      return RTA_E_NOMEM;
+    }
+    c->serve->cfg = *cfg;
+    c->serve->slots.resize((size_t)n_in);
+  }
+  const int st = create_impl(c, size, count, filters, lengths);
   if (st != RTA_OK) {
     free_all(c);
     delete c;
@@ -1010,6 +1588,24 @@ int rta_create_tuned(rta_ctx** out, double fs, int32_t block, const rta_scheme* 
   }
   *out = c;
   return RTA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rta_create_tuned(rta_ctx** out, double fs, int32_t block, const rta_scheme* scheme,
+                     int32_t n_in, int32_t n_out, const float* const* filters,
+                     const int64_t* lengths, int32_t spectra, uint32_t flags,
+                     const rta_tuning* tuning) {
+  if (out == nullptr) return RTA_E_ARG;
+  *out = nullptr;
+  std::vector<int> size, count;
+  int st = validate(fs, block, scheme, n_in, n_out, filters, lengths, spectra, flags, size, count);
+  if (st != RTA_OK) return st;
+  if (!tuning_ok(tuning)) return RTA_E_ARG;
+  return create_ctx(out, fs, block, size, count, n_in, n_out, filters, lengths, spectra, flags,
+                    tuning, nullptr);
 }
 
 int rta_create(rta_ctx** out, double fs, int32_t block, const rta_scheme* scheme, int32_t n_in,
@@ -1055,6 +1651,7 @@ int rta_reset(rta_ctx* c) {
   if (c == nullptr) return RTA_E_ARG;
   if (c->poisoned) return RTA_E_DEVICE;
   HIP_TRY(c, hipDeviceSynchronize());
+  if (c->serve != nullptr) return serve_reset(c);
   return zero_state(c);
 }
 
@@ -1082,7 +1679,7 @@ int rta_query(rta_ctx* c, rta_info* info) {
   info->io_bytes_per_block = c->io_bytes;
   info->cmacs_per_block = c->cmacs;
   info->tail_bytes_per_block = c->tail_bytes;
-  info->grid = c->head_slots + c->max_items;
+  info->grid = c->head_slots + c->grid_items;
   info->outputs_per_group = c->G;
   info->rows_per_item = c->rows_per_item;
   info->poisoned = c->poisoned ? 1 : 0;
@@ -1092,6 +1689,7 @@ int rta_query(rta_ctx* c, rta_info* info) {
 int rta_set_feedback(rta_ctx* c, const float* const* fb, const int64_t* lengths, int32_t spectra) {
   if (c == nullptr) return RTA_E_ARG;
   if (c->poisoned) return RTA_E_DEVICE;
+  if (c->serve != nullptr) return RTA_E_UNSUPPORTED;
   HIP_TRY(c, hipDeviceSynchronize());
   if (c->fc) {
     free_all(c->fc);
@@ -1225,6 +1823,89 @@ int rta_autotune(double fs, int32_t block, const rta_scheme* scheme, int32_t n_i
   return RTA_OK;
 }
 
+int rta_serve_create(rta_ctx** out, double fs, int32_t block, const rta_scheme* scheme,
+                     const rta_serve_config* cfg, int32_t spectra, uint32_t flags,
+                     const rta_tuning* tuning) {
+  if (out == nullptr) return RTA_E_ARG;
+  *out = nullptr;
+  if (cfg == nullptr || cfg->n_slots < 1 || cfg->n_out < 1 || cfg->max_taps < 1 ||
+      cfg->max_taps > (int64_t(1) << 31) || cfg->arena_bytes < 0 || !(cfg->budget_bytes >= 0.0) ||
+      !std::isfinite(cfg->budget_bytes))
+    return RTA_E_ARG;
+  if ((int64_t)cfg->n_slots * cfg->n_out > (1 << 20)) return RTA_E_ARG;
+  if (!tuning_ok(tuning)) return RTA_E_ARG;
+  // the tiers are laid out for max_taps on every pair; no taps are read
+  static const float dummy = 0.f;
+  const int64_t np = (int64_t)cfg->n_slots * cfg->n_out;
+  std::vector<const float*> f((size_t)np, &dummy);
+  std::vector<int64_t> len((size_t)np, cfg->max_taps);
+  std::vector<int> size, count;
+  const int st = validate(fs, block, scheme, cfg->n_slots, cfg->n_out, f.data(), len.data(), spectra,
+                          flags, size, count);
+  if (st != RTA_OK) return st;
+  return create_ctx(out, fs, block, size, count, cfg->n_slots, cfg->n_out, f.data(), len.data(),
+                    spectra, flags, tuning, cfg);
+}
+
+int rta_serve_admit(rta_ctx* c, const float* const* filters, const int64_t* lengths, int32_t* slot) {
+  if (c == nullptr || filters == nullptr || lengths == nullptr || slot == nullptr) return RTA_E_ARG;
+  if (c->serve == nullptr) return RTA_E_STATE;
+  if (c->poisoned) return RTA_E_DEVICE;
+  *slot = -1;
+  for (int l = 0; l < c->L; ++l) {
+    if (lengths[l] < 0 || lengths[l] > c->serve->cfg.max_taps) return RTA_E_ARG;
+    if (lengths[l] > 0 && filters[l] == nullptr) return RTA_E_ARG;
+  }
+  return serve_admit(c, filters, lengths, slot);
+}
+
+int rta_serve_release(rta_ctx* c, int32_t slot) {
+  if (c == nullptr) return RTA_E_ARG;
+  if (c->serve == nullptr) return RTA_E_STATE;
+  if (slot < 0 || slot >= c->Q) return RTA_E_ARG;
+  if (c->poisoned) return RTA_E_DEVICE;
+  return serve_release(c, slot);
+}
+
+int rta_serve_query(rta_ctx* c, rta_serve_info* info, rta_slot_info* slots) {
+  if (c == nullptr || info == nullptr) return RTA_E_ARG;
+  if (c->serve == nullptr) return RTA_E_STATE;
+  Serve* sv = c->serve;
+  std::memset(info, 0, sizeof(*info));
+  std::lock_guard<std::mutex> lk(sv->mu);
+  info->n_slots = c->Q;
+  for (size_t q = 0; q < sv->slots.size(); ++q) {
+    const ServeSlot& sl = sv->slots[q];
+    if (sl.state == RTA_SLOT_JOINING || sl.state == RTA_SLOT_LIVE) ++info->live;
+    else if (sl.state == RTA_SLOT_FREE) ++info->free_slots;
+    else ++info->draining;
+    if (present(sl.state)) info->bytes_per_block += sl.hb + sl.xb;
+    if (slots != nullptr) {
+      rta_slot_info& o = slots[q];
+      std::memset(&o, 0, sizeof(o));
+      o.state = sl.state;
+      const bool p = present(sl.state);
+      o.start_block = p ? sl.start : -1;
+      o.stop_block = p ? sl.stop : -1;
+      o.free_block = p ? sl.free_at : -1;
+      o.taps = p ? sl.taps : 0;
+      o.bytes_per_block = p ? sl.hb + sl.xb : 0.0;
+    }
+  }
+  const size_t eb = spectra_elem_bytes(c->dtype);
+  for (int t = 0; t < c->n_tiers; ++t) {
+    info->arena_bytes += sv->arena[t].capacity() * c->tier[t].P * (int64_t)eb;
+    info->arena_used_bytes += sv->arena[t].used() * c->tier[t].P * (int64_t)eb;
+  }
+  info->budget_bytes = sv->cfg.budget_bytes;
+  info->admitted = sv->admitted;
+  info->rejected_slots = sv->rej_slots;
+  info->rejected_memory = sv->rej_mem;
+  info->rejected_budget = sv->rej_budget;
+  info->plan_swaps = sv->swaps;
+  return c->poisoned ? RTA_E_DEVICE : RTA_OK;
+}
+
 int rta_destroy(rta_ctx* c) {
   if (c == nullptr) return RTA_OK;
   free_all(c);
@@ -1241,6 +1922,7 @@ const char* rta_strerror(int status) {
     case RTA_E_DEVICE: return "HIP runtime error (context poisoned)";
     case RTA_E_STATE: return "call not valid in the current state";
     case RTA_E_UNSUPPORTED: return "not supported by this build";
+    case RTA_E_CAPACITY: return "no free slot or per-block bandwidth budget exceeded";
     default: return "unknown status";
   }
 }

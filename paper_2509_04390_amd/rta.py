@@ -34,6 +34,10 @@ RTA_E_RANGE = -3
 RTA_E_DEVICE = -4
 RTA_E_STATE = -5
 RTA_E_UNSUPPORTED = -6
+RTA_E_CAPACITY = -7
+
+RTA_SLOT_FREE, RTA_SLOT_JOINING, RTA_SLOT_LIVE, RTA_SLOT_LEAVING, RTA_SLOT_DRAINING = range(5)
+SLOT_STATES = ("free", "joining", "live", "leaving", "draining")
 
 RTA_FP32, RTA_FP16, RTA_BF16 = 0, 1, 2
 DTYPES = {"fp32": RTA_FP32, "fp16": RTA_FP16, "bf16": RTA_BF16}
@@ -44,7 +48,8 @@ RTA_MAX_TIERS = 8
 EXPORTED = ("rta_create", "rta_process", "rta_process_device", "rta_reset",
             "rta_query", "rta_timing_enable", "rta_timing_read", "rta_probe_read",
             "rta_destroy", "rta_strerror", "rta_create_tuned", "rta_autotune",
-            "rta_set_feedback")
+            "rta_set_feedback", "rta_serve_create", "rta_serve_admit", "rta_serve_release",
+            "rta_serve_query")
 
 
 class rta_scheme(ctypes.Structure):
@@ -86,6 +91,29 @@ class rta_tuning(ctypes.Structure):
                 ("count", ctypes.c_int32 * RTA_MAX_TIERS)]
 
 
+class rta_serve_config(ctypes.Structure):
+    _fields_ = [("n_slots", ctypes.c_int32), ("n_out", ctypes.c_int32),
+                ("max_taps", ctypes.c_int64), ("arena_bytes", ctypes.c_int64),
+                ("budget_bytes", ctypes.c_double)]
+
+
+class rta_slot_info(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("start_block", ctypes.c_int64), ("stop_block", ctypes.c_int64),
+                ("free_block", ctypes.c_int64), ("taps", ctypes.c_int64),
+                ("bytes_per_block", ctypes.c_double)]
+
+
+class rta_serve_info(ctypes.Structure):
+    _fields_ = [("n_slots", ctypes.c_int32), ("live", ctypes.c_int32),
+                ("draining", ctypes.c_int32), ("free_slots", ctypes.c_int32),
+                ("arena_bytes", ctypes.c_int64), ("arena_used_bytes", ctypes.c_int64),
+                ("budget_bytes", ctypes.c_double), ("bytes_per_block", ctypes.c_double),
+                ("admitted", ctypes.c_int64), ("rejected_slots", ctypes.c_int64),
+                ("rejected_memory", ctypes.c_int64), ("rejected_budget", ctypes.c_int64),
+                ("plan_swaps", ctypes.c_int64)]
+
+
 _fp = ctypes.POINTER(ctypes.c_float)
 _lib.rta_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_double, ctypes.c_int32,
                             ctypes.POINTER(rta_scheme), ctypes.c_int32, ctypes.c_int32,
@@ -110,11 +138,21 @@ _lib.rta_probe_read.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
                                 ctypes.c_void_p]
 _lib.rta_timing_read.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
                                  ctypes.POINTER(ctypes.c_double)]
+_lib.rta_serve_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_double,
+                                  ctypes.c_int32, ctypes.POINTER(rta_scheme),
+                                  ctypes.POINTER(rta_serve_config), ctypes.c_int32,
+                                  ctypes.c_uint32, ctypes.POINTER(rta_tuning)]
+_lib.rta_serve_admit.argtypes = [ctypes.c_void_p, ctypes.POINTER(_fp),
+                                 ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]
+_lib.rta_serve_release.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+_lib.rta_serve_query.argtypes = [ctypes.c_void_p, ctypes.POINTER(rta_serve_info),
+                                 ctypes.POINTER(rta_slot_info)]
 _lib.rta_strerror.argtypes = [ctypes.c_int]
 _lib.rta_strerror.restype = ctypes.c_char_p
 for _f in ("rta_create", "rta_process", "rta_process_device", "rta_reset", "rta_query",
            "rta_timing_enable", "rta_timing_read", "rta_probe_read", "rta_destroy",
-           "rta_create_tuned", "rta_autotune", "rta_set_feedback"):
+           "rta_create_tuned", "rta_autotune", "rta_set_feedback", "rta_serve_create",
+           "rta_serve_admit", "rta_serve_release", "rta_serve_query"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -277,6 +315,52 @@ def rta_probe_read(d_buf: int, nbytes: int, grid: int, d_sink: int, stream: int 
            "rta_probe_read")
 
 
+def rta_serve_create(fs: float, block: int, scheme, n_slots: int, n_out: int, max_taps: int,
+                     arena_bytes: int = 0, budget_bytes: float = 0.0, spectra="fp32",
+                     flags: int = 0, tuning=None):
+    """Serving context with n_slots source slots and n_out outputs."""
+    _, _, _, sch = _marshal([None] * 1, 1, 1, None, scheme)
+    cfg = rta_serve_config(int(n_slots), int(n_out), int(max_taps), int(arena_bytes),
+                           float(budget_bytes))
+    dtype = DTYPES[spectra] if isinstance(spectra, str) else int(spectra)
+    ctx = ctypes.c_void_p()
+    st = _lib.rta_serve_create(ctypes.byref(ctx), float(fs), int(block),
+                               ctypes.byref(sch) if sch is not None else None,
+                               ctypes.byref(cfg), dtype, int(flags),
+                               ctypes.byref(tuning) if tuning is not None else None)
+    _check(st, "rta_serve_create")
+    return ctx
+
+
+def rta_serve_admit(ctx, filters) -> int:
+    """filters: n_out 1-D float32 arrays (None/empty = no path).  Returns the
+    slot; raises RtaError (status RTA_E_CAPACITY / RTA_E_NOMEM) on refusal."""
+    keep, ptrs, lens, _ = _marshal(list(filters), 1, len(filters), None, None)
+    slot = ctypes.c_int32(-1)
+    _check(_lib.rta_serve_admit(ctx, ptrs, lens, ctypes.byref(slot)), "rta_serve_admit")
+    return slot.value
+
+
+def rta_serve_release(ctx, slot: int) -> None:
+    _check(_lib.rta_serve_release(ctx, int(slot)), "rta_serve_release")
+
+
+def rta_serve_query(ctx, n_slots: Optional[int] = None):
+    """(info dict, list of per-slot dicts or None)."""
+    info = rta_serve_info()
+    slots = (rta_slot_info * n_slots)() if n_slots else None
+    _check(_lib.rta_serve_query(ctx, ctypes.byref(info), slots), "rta_serve_query")
+    d = {name: getattr(info, name) for name, _ in rta_serve_info._fields_}
+    per = None
+    if slots is not None:
+        per = []
+        for sl in slots:
+            e = {name: getattr(sl, name) for name, _ in rta_slot_info._fields_ if name != "pad"}
+            e["state"] = SLOT_STATES[sl.state]
+            per.append(e)
+    return d, per
+
+
 def rta_destroy(ctx) -> None:
     _check(_lib.rta_destroy(ctx), "rta_destroy")
 
@@ -373,3 +457,53 @@ class Convolver:
             self.process_device(xb[b], yb[b])
         torch.cuda.synchronize()
         return yb.permute(1, 0, 2).reshape(self.n_out, nb * self.block).cpu().numpy()
+
+
+class Server:
+    """A serving context: sources are admitted into slots and released while
+    blocks stream; ``process`` takes [n_slots][block] input."""
+
+    def __init__(self, n_slots: int, n_out: int, max_taps: int, block: int,
+                 fs: float = 48000.0, scheme=None, spectra="fp32", flags: int = 0,
+                 arena_bytes: int = 0, budget_bytes: float = 0.0, tuning=None):
+        self.n_slots, self.n_out, self.block = n_slots, n_out, block
+        self.ctx = None
+        self.ctx = rta_serve_create(fs, block, scheme, n_slots, n_out, max_taps, arena_bytes,
+                                    budget_bytes, spectra, flags, tuning)
+
+    def close(self):
+        if self.ctx is not None:
+            rta_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def admit(self, filters) -> int:
+        return rta_serve_admit(self.ctx, filters)
+
+    def release(self, slot: int) -> None:
+        rta_serve_release(self.ctx, slot)
+
+    def query(self):
+        return rta_serve_query(self.ctx, self.n_slots)
+
+    def info(self) -> dict:
+        return rta_query(self.ctx)
+
+    def reset(self):
+        rta_reset(self.ctx)
+
+    def process(self, block_in: np.ndarray) -> np.ndarray:
+        out = np.empty((self.n_out, self.block), np.float32)
+        rta_process(self.ctx, np.ascontiguousarray(block_in, dtype=np.float32), out)
+        return out

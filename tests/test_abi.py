@@ -40,7 +40,7 @@ def test_library_exports_every_declared_symbol(rta):
 
 
 def test_strerror_names_every_status(rta):
-    for code in (0, -1, -2, -3, -4, -5, -6):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
         assert rta.rta_strerror(code) and rta.rta_strerror(code) != "unknown status"
     assert rta.rta_strerror(-99) == "unknown status"
 
@@ -58,6 +58,46 @@ def test_destroy_null_and_null_handles_are_rejected(rta):
     assert lib.rta_create(None, 48000.0, 128, None, 1, 1, None, None, 0, 0) == rta.RTA_E_ARG
     assert lib.rta_create_tuned(None, 48000.0, 128, None, 1, 1, None, None, 0, 0, None) == rta.RTA_E_ARG
     assert lib.rta_autotune(48000.0, 128, None, 1, 1, None, None, 0, 0, 8, None, None) == rta.RTA_E_ARG
+    assert lib.rta_serve_admit(None, None, None, None) == rta.RTA_E_ARG
+    assert lib.rta_serve_release(None, 0) == rta.RTA_E_ARG
+    assert lib.rta_serve_query(None, None, None) == rta.RTA_E_ARG
+
+
+@pytest.mark.parametrize("cfg", [
+    None,
+    dict(n_slots=0),
+    dict(n_out=0),
+    dict(max_taps=0),
+    dict(max_taps=(1 << 31) + 1),
+    dict(arena_bytes=-1),
+    dict(budget_bytes=-1.0),
+    dict(budget_bytes=float("nan")),
+    dict(n_slots=2048, n_out=1024),          # more than 2^20 pairs
+    dict(block=100),                         # not a power of two
+    dict(scheme=[(128, 8), (1024, 0)]),      # o_1 = 1024 < P_1 + B
+    dict(tuning=4),                          # G = 3
+])
+def test_invalid_serving_configs_are_rejected_before_any_device_call(rta, cfg):
+    args = dict(n_slots=4, n_out=8, max_taps=48000, arena_bytes=0, budget_bytes=0.0,
+                block=128, scheme=None, tuning=None)
+    if cfg is not None:
+        args.update(cfg)
+    c = None
+    if cfg is not None:
+        c = rta.rta_serve_config(args["n_slots"], args["n_out"], args["max_taps"],
+                                 args["arena_bytes"], args["budget_bytes"])
+    sch = None
+    if args["scheme"] is not None:
+        sizes = (ctypes.c_int32 * 2)(*[s for s, _ in args["scheme"]])
+        counts = (ctypes.c_int32 * 2)(*[n for _, n in args["scheme"]])
+        sch = rta.rta_scheme(2, sizes, counts)
+    tun = rta.make_tuning(outputs_per_group=3) if args["tuning"] else None
+    ctx = ctypes.c_void_p()
+    st = rta._lib.rta_serve_create(ctypes.byref(ctx), 48000.0, args["block"],
+                                   ctypes.byref(sch) if sch is not None else None,
+                                   ctypes.byref(c) if c is not None else None, 0, 0,
+                                   ctypes.byref(tun) if tun is not None else None)
+    assert st == rta.RTA_E_ARG and not ctx.value
 
 
 def _create_status(rta, fs=48000.0, block=128, scheme=None, n_in=1, n_out=1,
