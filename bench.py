@@ -245,6 +245,97 @@ def serve_bench(args, torch, rta, workloads) -> dict:
     }
 
 
+def sweep_point(torch, rta, workloads, B, L, seconds, fs, spectra, fb_seconds=None,
+                steps=400, paced=300, seed=11):
+    """One point of the paper's sweeps (Sec. VI, Figs. 3-6): 1 input -> L
+    outputs with `seconds`-long filters at block B; optionally feedback
+    cancellation with one microphone and L feedback paths of fb_seconds.
+    Returns mean device-path block time and paced host-path latency."""
+    n_h = max(1, int(round(seconds * fs)))
+    filt = workloads.reverb_filters(seed, 1, L, n_h, (6.0, 10.0), int(fs))
+    cv = rta.Convolver(filt, B, fs=fs, spectra=spectra)
+    if fb_seconds is not None:
+        n_f = max(1, int(round(fb_seconds * fs)))
+        fb = workloads.reverb_filters(seed + 1, 1, L, n_f, (0.3, 0.3), int(fs))
+        cv.set_feedback([[(0.001 * f).astype(np.float32) for f in fb[0]]])
+    x = workloads.white_noise(seed + 2, 1, 64 * B)
+    xb = torch.from_numpy(x.reshape(1, 64, B).transpose(1, 0, 2).copy()).cuda()
+    yb = torch.empty((64, L, B), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    sh = stream.cuda_stream
+    launch = rta._lib.rta_process_device
+    pin = [xb[i].data_ptr() for i in range(64)]
+    pout = [yb[i].data_ptr() for i in range(64)]
+    for i in range(64):
+        launch(cv.ctx, pin[i], pout[i], sh)
+    rta.rta_timing_enable(cv.ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        if launch(cv.ctx, pin[k % 64], pout[k % 64], sh) != 0:
+            raise RuntimeError("rta_process_device failed")
+    torch.cuda.synchronize()
+    us = 1e6 * (time.perf_counter() - t0) / steps
+    n_timed, kern_ms = rta.rta_timing_read(cv.ctx)
+    rta.rta_timing_enable(cv.ctx, False)
+    out = np.empty((L, B), np.float32)
+    blocks = [np.ascontiguousarray(x[:, i * B:(i + 1) * B]) for i in range(64)]
+    for i in range(16):
+        rta.rta_process(cv.ctx, blocks[i], out)
+    lat = []
+    period = B / fs
+    paced = max(20, min(paced, int(2.0 / period)))  # at most about 2 s of audio
+    nxt = time.perf_counter()
+    for i in range(paced):
+        nxt += period
+        t = time.perf_counter()
+        rta.rta_process(cv.ctx, blocks[i % 64], out)
+        lat.append(time.perf_counter() - t)
+        rem = nxt - time.perf_counter()
+        if rem > 3e-4:
+            time.sleep(rem - 2e-4)
+        while time.perf_counter() < nxt:
+            pass
+    info = cv.info()
+    cv.close()
+    lat_us = np.array(lat) * 1e6
+    deadline = rta.deadline_us(B, fs)
+    return {"block": B, "n_out": L, "filter_s": seconds, "fb_filter_s": fb_seconds,
+            "us_per_block": us, "kernel_us": 1e3 * kern_ms / max(1, n_timed),
+            "x_real_time": (B / fs) / (us * 1e-6), "deadline_us": deadline,
+            "paced_p50_us": float(np.percentile(lat_us, 50)),
+            "paced_p99_us": float(np.percentile(lat_us, 99)),
+            "paced_max_us": float(lat_us.max()), "xruns": int(np.sum(lat_us > deadline)),
+            "spectra_mb": info["spectra_bytes"] / 1e6}
+
+
+def sweeps(args, torch, rta, workloads) -> dict:
+    """The paper's four sweeps around its defaults (32 outputs, 10 s filters,
+    B = 128, 48 kHz): block size, filter length, output channels, and the
+    feedback-cancellation filter length."""
+    fs = 48000.0
+    spectra = args.spectra or "fp32"
+    which = args.sweep.split(",")
+    if "all" in which:
+        which = ["block", "length", "outputs", "feedback"]
+    grid = {
+        "block": [dict(B=b, L=32, seconds=10.0) for b in (16, 32, 64, 128, 256, 512, 1024, 2048, 4096)],
+        "length": [dict(B=128, L=32, seconds=s) for s in (0.1, 0.5, 1.0, 2.0, 5.0, 10.0, 15.0, 20.0)],
+        "outputs": [dict(B=128, L=l, seconds=10.0) for l in (1, 2, 4, 8, 16, 32, 64, 96, 120, 128)],
+        "feedback": [dict(B=128, L=32, seconds=10.0, fb_seconds=s) for s in (0.1, 0.5, 1.0, 2.0, 5.0)],
+    }
+    res = {}
+    for name in which:
+        pts = []
+        for kw in grid[name]:
+            pt = sweep_point(torch, rta, workloads, fs=fs, spectra=spectra, **kw)
+            log(f"sweep {name}: {json.dumps(pt)}")
+            pts.append(pt)
+        res[name] = pts
+    return {"sweeps": res, "spectra": spectra, "fs": fs,
+            "defaults": "1 input -> 32 outputs, 10 s filters, B = 128"}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -264,6 +355,8 @@ def main() -> int:
     ap.add_argument("--copy-probe-mb", type=int, default=0)
     ap.add_argument("--autotune", action="store_true",
                     help="run the library's autotuner first and use its scheme and tiling")
+    ap.add_argument("--sweep", default=None,
+                    help="comma list of block,length,outputs,feedback or 'all': the paper's sweeps")
     ap.add_argument("--serve", action="store_true",
                     help="serving with continuous batching (16 slots x 64 out x 12 s, B=64)")
     ap.add_argument("--serve-seconds", type=float, default=20.0)
@@ -292,6 +385,9 @@ def main() -> int:
 
     if args.serve:
         print(json.dumps(serve_bench(args, torch, rta, workloads)))
+        return 0
+    if args.sweep:
+        print(json.dumps(sweeps(args, torch, rta, workloads)))
         return 0
 
     wl = workloads.config(args.workload)
