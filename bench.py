@@ -268,7 +268,7 @@ def sweep_point(torch, rta, workloads, B, L, seconds, fs, spectra, fb_seconds=No
     pout = [yb[i].data_ptr() for i in range(64)]
     for i in range(64):
         launch(cv.ctx, pin[i], pout[i], sh)
-    rta.rta_timing_enable(cv.ctx, True)
+    rta.rta_timing_enable(cv.ctx, 16)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
@@ -355,6 +355,12 @@ def main() -> int:
     ap.add_argument("--copy-probe-mb", type=int, default=0)
     ap.add_argument("--autotune", action="store_true",
                     help="run the library's autotuner first and use its scheme and tiling")
+    ap.add_argument("--timing-every", type=int, default=16,
+                    help="time spans of this many consecutive blocks with two HIP events each "
+                         "(event packets on every block would slow the stream down)")
+    ap.add_argument("--tile", default=None,
+                    help="explicit tiling G:items:slices (outputs per group, first-tier items, "
+                         "bin slices per row); 0 keeps a default")
     ap.add_argument("--sweep", default=None,
                     help="comma list of block,length,outputs,feedback or 'all': the paper's sweeps")
     ap.add_argument("--serve", action="store_true",
@@ -406,6 +412,9 @@ def main() -> int:
     x = wl_steps.signal_array()
 
     tuning, tuned = None, None
+    if args.tile:
+        g_, it_, sl_ = (int(v) for v in args.tile.split(":"))
+        tuning = rta.make_tuning(outputs_per_group=g_, tail_items=it_, bin_slices=sl_)
     if args.autotune:
         t0 = time.perf_counter()
         tuning, chosen, us = rta.rta_autotune(fs, B, scheme, Q, L, filt, spectra=args.spectra,
@@ -436,7 +445,7 @@ def main() -> int:
     pout = [yb[i].data_ptr() for i in range(nblk)]
     sh = stream.cuda_stream
     launch = rta._lib.rta_process_device
-    rta.rta_timing_enable(cv.ctx, True)
+    rta.rta_timing_enable(cv.ctx, args.timing_every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -451,8 +460,8 @@ def main() -> int:
     ms_per_step = 1e3 * wall / args.steps
     audio_per_step = B / fs
     value = audio_per_step / (ms_per_step / 1e3)
-    log(f"timed {args.steps} steps: {ms_per_step * 1e3:.1f} us/step; k_block {kern_us:.1f} us "
-        f"(mean of {n_timed})")
+    log(f"timed {args.steps} steps: {ms_per_step * 1e3:.1f} us/step; {kern_us:.1f} us per block "
+        f"in event-timed spans of {args.timing_every} ({n_timed} blocks)")
     probes = read_probes(torch, rta, int(info["spectra_bytes"]), info["grid"], stream)
 
     # synchronous host-memory blocks: per-block latency including PCIe (after
@@ -488,6 +497,7 @@ def main() -> int:
                  "mode": "rta_process paced every B/fs, host memory, PCIe included",
                  "p50_us": float(np.percentile(plat_us, 50)),
                  "p99_us": float(np.percentile(plat_us, 99)), "max_us": float(plat_us.max()),
+                 "max_at_block": int(np.argmax(plat_us)),
                  "xruns": int(np.sum(plat_us > deadline))}
 
     bytes_per_launch = (info["h_bytes_per_block"] + info["x_bytes_per_block"]
@@ -534,6 +544,8 @@ def main() -> int:
                                  "p50_us": float(np.percentile(lat_us, 50)),
                                  "p99_us": float(np.percentile(lat_us, 99)),
                                  "max_us": float(lat_us.max()),
+                                 "max_at_block": int(np.argmax(lat_us)),
+                                 "over_1ms": int(np.sum(lat_us > 1000.0)),
                                  "xruns": int(np.sum(lat_us > deadline))},
         "roofline": {
             "kernel": "k_block",
@@ -545,6 +557,10 @@ def main() -> int:
             "traffic": traffic,
             "bytes_per_launch": bytes_per_launch,
             "kernel_us_mean": kern_us,
+            "kernel_us_timing": (f"HIP events on the launch stream around spans of "
+                                 f"{args.timing_every} back-to-back blocks inside the timed "
+                                 f"region ({n_timed} blocks): per-block time including the "
+                                 "gaps between launches, an upper bound on the kernel's"),
         },
         "read_probe": probes,
         "autotune": tuned,

@@ -142,12 +142,17 @@ int rta_create(rta_ctx** out, double fs, int32_t block,
  *                      items per block (default 1024).
  *   tail_rows          partitions per first-tier item; overrides tail_items.
  *   tier_rows          partitions per later-tier item (default 16).
+ *   bin_slices         S in {1, 2, 4, 8}: first-tier items cover 1/S of a
+ *                      partition row's bins over S times more rows, so each
+ *                      output group owns S times fewer partial sums for the
+ *                      output workgroups to reduce (default 1).
  * rta_autotune() also fills the scheme it selected (n_tiers, size, count). */
 typedef struct rta_tuning {
     int32_t outputs_per_group;
     int32_t tail_items;
     int32_t tail_rows;
     int32_t tier_rows;
+    int32_t bin_slices;
     int32_t n_tiers;
     int32_t size[RTA_MAX_TIERS];
     int32_t count[RTA_MAX_TIERS];
@@ -166,7 +171,7 @@ int rta_create_tuned(rta_ctx** out, double fs, int32_t block,
  * 16B, 64B), each tier starting exactly 2 P_t - B taps into the filter,
  * limited to tiers the longest filter reaches and to sizes <= 8192.  For
  * every candidate scheme and tiling (G in {1, 2, 4} x tail_items in {512,
- * 1024, 2048}) a context is created, `blocks` blocks of zero input are run
+ * 1024, 2048} x bin_slices in {1, 2, 4}) a context is created, `blocks` blocks of zero input are run
  * through rta_process_device() after 16 warm-up blocks, and the mean block
  * time is measured with HIP events.  The fastest is written to *best and its
  * mean block time in microseconds to *best_us.  Takes one to a few seconds
@@ -223,16 +228,22 @@ int rta_reset(rta_ctx* ctx);
 /* Fill *info with the context's geometry and counters (no device call). */
 int rta_query(rta_ctx* ctx, rta_info* info);
 
-/* Kernel timing (profiling aid).  Each block is one kernel launch (the heads
+/* Block timing (profiling aid).  Each block is one kernel launch (the heads
  * of this block and the multiply-accumulate of partitions >= 2 for the next
- * one).  After rta_timing_enable(ctx, 1), every block launched by
- * rta_process() or rta_process_device() records two HIP events on its launch
- * stream, just before and just after the kernel.  rta_timing_read() waits
- * for the recorded events, returns the number of timed blocks and the summed
- * kernel durations in milliseconds, then forgets them.  Blocks beyond 65536
- * are not recorded.  rta_timing_enable(ctx, 0) stops recording. */
-int rta_timing_enable(rta_ctx* ctx, int32_t on);
-int rta_timing_read(rta_ctx* ctx, int64_t* blocks, double* kernel_ms);
+ * one; with later tiers or feedback paths, a second and third launch).
+ * After rta_timing_enable(ctx, every) with every >= 1, the blocks launched by
+ * rta_process() or rta_process_device() are timed in spans of `every`
+ * consecutive blocks, each starting at a block index that is a multiple of
+ * `every`: one HIP event on the launch stream before the span's first launch
+ * and one after its last.  With every = 1 that brackets each block's kernels;
+ * a longer span also counts the gaps between back-to-back launches but keeps
+ * the event packets, which delay the stream, off most blocks.
+ * rta_timing_read() waits for the recorded events and returns the number of
+ * blocks in complete spans and their summed time in milliseconds, then
+ * forgets them.  At most 65536 spans are kept.  rta_timing_enable(ctx, 0)
+ * stops recording (a span still open is dropped); every < 0 is RTA_E_ARG. */
+int rta_timing_enable(rta_ctx* ctx, int32_t every);
+int rta_timing_read(rta_ctx* ctx, int64_t* blocks, double* block_ms);
 
 /* Measurement aid, independent of any context: launch a streaming-read
  * kernel over the first floor(bytes/16)*16 bytes of device memory d_buf

@@ -9,8 +9,8 @@
 // that were in the delay line one block earlier.  Launch n of k_block
 // therefore runs two kinds of workgroups side by side:
 //
-//   head workgroups (one per output group, dispatched first, latency
-//   critical): real FFT of each input's window [x_{n-1}, x_n] (Sec. IV step
+//   head workgroups (one per output, dispatched first, latency critical):
+//   real FFT of each input's window [x_{n-1}, x_n] (Sec. IV step
 //   1, batched in LDS), store it into ring slot n mod K, add
 //   sum_q H_{l,q,0} X_q(n) + H_{l,q,1} X_q(n-1) to the partial sums of the
 //   terms p >= 2 that the previous launch prepared, inverse real FFT, keep
@@ -52,7 +52,7 @@ enum ItemKind : int32_t {
 
 struct Item {          // one workgroup's work in one block (48 bytes)
   int32_t kind;        // ItemKind
-  int32_t flags;
+  int32_t w;           // K_MAC: bins of the slice (divides P; W/C lanes per row)
   int32_t tier;
   int32_t group;       // reduction group (outputs l0 .. l0+nl-1)
   int32_t q;           // input channel
@@ -97,7 +97,7 @@ struct KArgs {
   int32_t B, Q, L, n_tiers;
   int32_t n_phase, max_items;
   int32_t head_nq;           // inputs transformed per pass by a head
-  int32_t n_head;            // head workgroups (output groups)
+  int32_t n_head;            // head workgroups (one per output)
   int32_t head_slots;        // head part of the grid (n_head rounded up to 8)
   int32_t pad;
   int64_t n;                 // index of the block of this launch
@@ -199,7 +199,7 @@ __device__ void mac_item(const KArgs& A, const DevTier& T, const Item& it,
                          const Group& grp, int64_t frame, float2* red) {
   constexpr int C = HVec<HT>::C;
   const int P = T.P;
-  const int W = P < kThreads * C ? P : kThreads * C;  // bins per item slice
+  const int W = it.w;                                  // bins per item slice
   const int LR = W / C;                                // lanes per row
   const int RP = kThreads / LR;                        // rows per pass
   const int tid = threadIdx.x;
@@ -384,12 +384,14 @@ __device__ void head_reduce(const KArgs& A, const DevTier& T, const Group& grp, 
   const bool has_p1 = T.K >= 2;
   const int slot1 = wrap_slot(n - 1, T.K);
   const HT* H01 = reinterpret_cast<const HT*>(A.H01);
-  auto p1_term = [&](int e) {
+  // inputs q0, q0 + dq, ... of the p = 1 term of element e
+  auto p1_term = [&](int e, int q0, int dq) {
     float2 t = make_float2(0.f, 0.f);
     if (!has_p1) return t;
     const int g = e / P, k = e - g * P;
     const int l = grp.l0 + g;
-    for (int q = 0; q < A.Q; ++q) {
+#pragma unroll 4
+    for (int q = q0; q < A.Q; q += dq) {
       const float2 h1 = HVec<HT>::load1(H01 + ((int64_t)(l * A.Q + q) * 2 + 1) * P + k);
       const float2 x1 = T.X[((int64_t)q * T.K + slot1) * P + k];
       t = cadd(t, (k == 0) ? make_float2(h1.x * x1.x, h1.y * x1.y) : cmul(h1, x1));
@@ -398,7 +400,7 @@ __device__ void head_reduce(const KArgs& A, const DevTier& T, const Group& grp, 
   };
   if (E >= kThreads) {
     for (int e = tid; e < E; e += kThreads) {
-      float2 acc = p1_term(e);
+      float2 acc = p1_term(e, 0, 1);
 #pragma unroll 16
       for (int sl = 0; sl < grp.nslot; ++sl) acc = cadd(acc, base[sl * stride + e]);
       Y[e] = acc;
@@ -412,7 +414,7 @@ __device__ void head_reduce(const KArgs& A, const DevTier& T, const Group& grp, 
   if (tg < ng) {
     const int per = (grp.nslot + ng - 1) / ng;
     const int s0 = min(grp.nslot, tg * per), s1 = min(grp.nslot, s0 + per);
-    if (tg == 0) acc = p1_term(e);
+    acc = p1_term(e, tg, ng);  // the thread groups split the inputs
 #pragma unroll 16
     for (int sl = s0; sl < s1; ++sl) acc = cadd(acc, base[sl * stride + e]);
   }
@@ -443,14 +445,18 @@ __host__ __device__ inline HeadLds head_lds(int P, int G, int nq) {
   return h;
 }
 
-// Head workgroup: output group `grp` of block n (see the top of the file).
+// Head workgroup of block n for one output: `grp` is the single-output group
+// {l, 1} and gsel the output's index within its tail group of G outputs (its
+// row in every partial slot).  One head per output keeps each head's share
+// of the partial-sum reduction, the critical path under the tails' streaming,
+// independent of G.
 template <typename HT, int G>
-__device__ void head_work(const KArgs& A, const Group& grp, float2* lds) {
+__device__ void head_work(const KArgs& A, const Group& grp, int gsel, float2* lds) {
   const int tid = threadIdx.x;
   const int64_t n = A.n;
   const DevTier& T = A.tier[0];
   const int P = T.P, logP = T.logP;  // P == B
-  const HeadLds L = head_lds(P, G, A.head_nq);
+  const HeadLds L = head_lds(P, 1, A.head_nq);
   float2* Y = lds + L.y;
   float2* Xa = lds + L.xa;
   float2* Xb = lds + L.xb;
@@ -536,7 +542,7 @@ __device__ void head_work(const KArgs& A, const Group& grp, float2* lds) {
   //    term p = 1 (ring slot n-1)
   const DevTier Tcur = [&] {
     DevTier t = T;
-    t.partial = T.partial + (n & 1) * (int64_t)T.nslots * G * P;
+    t.partial = T.partial + (n & 1) * (int64_t)T.nslots * G * P + (int64_t)gsel * P;
     return t;
   }();
   head_reduce<HT, G>(A, Tcur, grp, n, Y, scratch);
@@ -588,6 +594,7 @@ __device__ void head_work(const KArgs& A, const Group& grp, float2* lds) {
       for (int e = tid; e < E; e += kThreads) {
         const int k = e % P;
         float2 acc = Y[e];
+#pragma unroll 4
         for (int b = 0; b < nb; ++b) {
           const float2 h0 = h0_at(e, q0 + b);
           const float2 x0 = x[b * P + k];
@@ -677,7 +684,13 @@ __global__ __launch_bounds__(kThreads) void k_block(const KArgs A) {
   extern __shared__ float2 lds[];
   const int b = blockIdx.x;
   if (b < A.head_slots) {
-    if (b < A.n_head) head_work<HT, G>(A, A.groups[b], lds);
+    if (b < A.n_head) {  // head b: output b, in group b / G
+      const Group g0 = A.groups[b / G];
+      Group hg = g0;
+      hg.l0 = b;
+      hg.nl = 1;
+      head_work<HT, G>(A, hg, b - g0.l0, lds);
+    }
     return;
   }
   const int phase = (int)(A.n % A.n_phase);

@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -76,6 +77,7 @@ struct rta_ctx {
   TierHost tier[kMaxTiers];
   int G = 1, rows_per_item = 0, n_phase = 1, max_items = 0, n_items = 0;
   int tail_items = 1024, tier_rows = 16;
+  int bin_slices = 1;          // first-tier bin slices per partition row
   int n_groups = 0, head_slots = 0, head_nq = 1;
   int64_t hist_len = 0, ring_len = 0;
   size_t lds = 0;              // k_block dynamic LDS
@@ -111,7 +113,9 @@ struct rta_ctx {
   Serve* serve = nullptr;         // serving state (rta_serve_create)
 
   bool poisoned = false;
-  bool timing = false;
+  int timing = 0;                  // timed spans of this many blocks (0: off)
+  bool span_open = false;          // a span's first event is recorded
+  int timing_span_read = 1;        // blocks per recorded span
   std::vector<hipEvent_t> events;  // 2 per timed block
   size_t events_used = 0;
   int64_t device_bytes = 0, spectra_bytes = 0;
@@ -375,12 +379,16 @@ std::vector<Item> place_on_xcds(std::vector<Bucket>& buckets) {
   return flat;
 }
 
+// A bucket holds every bin slice of one partition range (all of each row's
+// bytes): an XCD that streamed only one byte range of every row would reach
+// only part of the HBM channels (measured: the XCDs holding one slice of two
+// finished 3 us after the others).
 void add_to_bucket(std::vector<Bucket>& buckets, const Item& it, int nl) {
   auto bit = std::find_if(buckets.begin(), buckets.end(), [&](const Bucket& b) {
-    return b.tier == it.tier && b.q == it.q && b.p0 == it.p0 && b.k0 == it.k0;
+    return b.tier == it.tier && b.q == it.q && b.p0 == it.p0;
   });
   if (bit == buckets.end()) {
-    buckets.push_back(Bucket{it.tier, it.q, it.p0, it.k0, {}, 0});
+    buckets.push_back(Bucket{it.tier, it.q, it.p0, 0, {}, 0});
     bit = buckets.end() - 1;
   }
   bit->items.push_back(it);
@@ -415,7 +423,12 @@ int build_plan(rta_ctx* c, Plan& plan) {
   std::vector<Item> tier0;
   {
     TierHost& T = c->tier[0];
-    const int P = T.P, W = std::min(P, kThreads * C), nslice = P / W;
+    // bin slices per row: each item covers W bins of nslice-fold more rows,
+    // so an output group owns nslice-fold fewer partial slots for the heads
+    // to reduce; a wave still reads whole 16-byte-per-lane segments of
+    // 64 / (W / C) rows
+    const int Wmax = std::min(T.P, kThreads * C);
+    const int W = std::max(C, Wmax / std::max(1, c->bin_slices)), nslice = T.P / W;
     int64_t total_rows = 0;
     for (const Group& gr : plan.groups)
       for (int q = 0; q < c->Q; ++q) total_rows += std::max(0, group_rows(T, gr, q) - 2);
@@ -457,6 +470,7 @@ int build_plan(rta_ctx* c, Plan& plan) {
             it.p0 = p0;
             it.p1 = p1;
             it.k0 = sl * W;
+            it.w = W;
             it.slot = it_slot;
             tier0.push_back(it);
           }
@@ -543,6 +557,7 @@ int build_plan(rta_ctx* c, Plan& plan) {
           it.p0 = chunks[i].p0;
           it.p1 = chunks[i].p1;
           it.k0 = sl * W;
+          it.w = W;
           it.slot = chunks[i].slot;
           it.lag = lag;
           tier_mac[(ph0 + lag) % n_phase].push_back(it);
@@ -587,9 +602,10 @@ int build_plan(rta_ctx* c, Plan& plan) {
       if (it.kind != K_MAC || it.tier < 0 || it.tier >= c->n_tiers) return RTA_E_STATE;
       if (it.group < 0 || it.group >= ngroups) return RTA_E_STATE;
       const TierHost& T = c->tier[it.tier];
-      const int W = std::min(T.P, kThreads * C);
+      const int W = it.w;
       if (it.q < 0 || it.q >= c->Q) return RTA_E_STATE;
       if (it.p0 < (it.tier == 0 ? 2 : 0) || it.p1 < it.p0 || it.p1 > T.K) return RTA_E_STATE;
+      if (W < C || W > kThreads * C || (W & (W - 1)) != 0 || T.P % W != 0) return RTA_E_STATE;
       if (it.k0 < 0 || it.k0 % W != 0 || it.k0 + W > T.P) return RTA_E_STATE;
       if (it.tier == 0) {
         const Group& gr = plan.groups[it.group];
@@ -645,7 +661,7 @@ KArgs make_args(const rta_ctx* c, const float* in, float* out, int64_t n) {
   a.n_phase = c->n_phase;
   a.max_items = c->max_items;
   a.head_nq = c->head_nq;
-  a.n_head = c->n_groups;
+  a.n_head = c->L;
   a.head_slots = c->head_slots;
   a.n = n;
   a.H01 = c->H01;
@@ -743,16 +759,21 @@ int launch_block(rta_ctx* c, const float* in, float* out, hipStream_t s, bool fl
   const unsigned grid = (unsigned)(c->head_slots + c->grid_items);
   const int phase = (int)(c->block % c->n_phase);
   const int n_tier = c->tier_count_host.empty() ? 0 : c->tier_count_host[phase];
-  hipEvent_t* e = nullptr;
-  if (c->timing && c->events_used + 2 <= 2 * kMaxTimedBlocks) {
+  // timing: a span of `timing` consecutive blocks starts at every block
+  // index that is a multiple of it; an event before its first launch and one
+  // after its last
+  const int64_t every = c->timing;
+  const bool span_start = every > 0 && c->block % every == 0 &&
+                          c->events_used + 2 <= 2 * kMaxTimedBlocks;
+  const bool span_end = every > 0 && c->span_open && (c->block + 1) % every == 0;
+  if (span_start) {
     while (c->events.size() < c->events_used + 2) {
       hipEvent_t ev;
       HIP_TRY(c, hipEventCreate(&ev));
       c->events.push_back(ev);
     }
-    e = &c->events[c->events_used];
-    c->events_used += 2;
-    HIP_TRY(c, hipEventRecord(e[0], s));
+    HIP_TRY(c, hipEventRecord(c->events[c->events_used], s));
+    c->span_open = true;
   }
   if (c->fc != nullptr) {
     a.sub = c->d_c;
@@ -771,7 +792,11 @@ int launch_block(rta_ctx* c, const float* in, float* out, hipStream_t s, bool fl
       return st;
     }
   }
-  if (e) HIP_TRY(c, hipEventRecord(e[1], s));
+  if (span_end || (span_start && every == 1)) {
+    HIP_TRY(c, hipEventRecord(c->events[c->events_used + 1], s));
+    c->events_used += 2;
+    c->span_open = false;
+  }
   c->block += 1;
   return RTA_OK;
 }
@@ -961,7 +986,7 @@ int serve_lists(rta_ctx* c, Plan& plan) {
     if (cap.groups[g].slot0 != plan.groups[g].slot0 || cap.groups[g].nslot != plan.groups[g].nslot)
       return RTA_E_STATE;
   c->n_groups = (int)plan.groups.size();
-  c->head_slots = (c->n_groups + kXcds - 1) / kXcds * kXcds;
+  c->head_slots = (c->L + kXcds - 1) / kXcds * kXcds;
   size_t mb = 1, mt = 1;
   for (int ph = 0; ph < c->n_phase; ++ph) {
     mb = std::max(mb, cap.block[ph].size());
@@ -1098,8 +1123,7 @@ int create_impl(rta_ctx* c, const std::vector<int>& size, const std::vector<int>
   // outputs per group: as requested, halved until a head's LDS fits
   int max_lds = 0;
   HIP_TRY(c, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
-  while (c->G > 1 && (int64_t)sizeof(float2) * head_lds(c->tier[0].P, c->G, 1).total + 64 > max_lds)
-    c->G /= 2;
+
 
   // work lists
   Plan plan;
@@ -1108,7 +1132,7 @@ int create_impl(rta_ctx* c, const std::vector<int>& size, const std::vector<int>
   } else {
   if ((st = build_plan(c, plan)) != RTA_OK) return st;
   c->n_groups = (int)plan.groups.size();
-  c->head_slots = (c->n_groups + kXcds - 1) / kXcds * kXcds;  // keeps tails' XCD residues
+  c->head_slots = (c->L + kXcds - 1) / kXcds * kXcds;  // keeps tails' XCD residues
   size_t mb = 1, mt = 1;
   for (int ph = 0; ph < c->n_phase; ++ph) {
     mb = std::max(mb, plan.block[ph].size());
@@ -1173,9 +1197,9 @@ int create_impl(rta_ctx* c, const std::vector<int>& size, const std::vector<int>
   // reduction.  head_nq: as many inputs per pass as fit in 48 KB, at least 1.
   const int C = vec_bins(c->dtype);
   const int P0 = c->tier[0].P;
-  const int fixed = head_lds(P0, c->G, 1).total - 2 * std::max(1, c->G) * P0;
+  const int fixed = head_lds(P0, 1, 1).total - 2 * P0;
   c->head_nq = std::max(1, std::min(c->Q, (6144 - fixed) / (2 * P0)));
-  c->lds = sizeof(float2) * std::max((size_t)head_lds(P0, c->G, c->head_nq).total,
+  c->lds = sizeof(float2) * std::max((size_t)head_lds(P0, 1, c->head_nq).total,
                                      (size_t)kThreads * C * c->G);
   if ((int64_t)c->lds + 64 > (int64_t)max_lds) return RTA_E_UNSUPPORTED;
   if (c->lds > 65536)
@@ -1546,8 +1570,9 @@ int serve_reset(rta_ctx* c) {
 bool tuning_ok(const rta_tuning* tuning) {
   if (tuning == nullptr) return true;
   const int g = tuning->outputs_per_group;
+  const int s = tuning->bin_slices;
   return !((g != 0 && g != 1 && g != 2 && g != 4) || tuning->tail_items < 0 || tuning->tail_rows < 0 ||
-           tuning->tier_rows < 0);
+           tuning->tier_rows < 0 || (s != 0 && s != 1 && s != 2 && s != 4 && s != 8));
 }
 
 int create_ctx(rta_ctx** out, double fs, int32_t block, const std::vector<int>& size,
@@ -1570,6 +1595,7 @@ int create_ctx(rta_ctx** out, double fs, int32_t block, const std::vector<int>& 
     if (tuning->tail_items) c->tail_items = tuning->tail_items;
     if (tuning->tail_rows) c->rows_per_item = tuning->tail_rows;
     if (tuning->tier_rows) c->tier_rows = tuning->tier_rows;
+    if (tuning->bin_slices) c->bin_slices = tuning->bin_slices;
   }
   if (cfg != nullptr) {
     c->serve = new (std::nothrow) Serve();
@@ -1623,11 +1649,15 @@ int rta_process(rta_ctx* c, const float* in, float* out) {
   int st = launch_block(c, c->m_in, c->m_out, c->stream, true);
   if (st != RTA_OK) return st;
   // spin until the last head has raised the flag; the tail workgroups of the
-  // same launch keep running.  Every few thousand polls the stream is asked
-  // for errors so a failed launch cannot spin forever.
+  // same launch keep running.  No runtime call on the normal path: only once
+  // the flag is 2 ms late is the stream asked for errors (then every 1 ms),
+  // so a failed launch cannot spin forever.
+  using clk = std::chrono::steady_clock;
+  const clk::time_point t0 = clk::now();
+  clk::time_point next_check = t0 + std::chrono::milliseconds(2);
   for (uint64_t i = 1;; ++i) {
     if (__atomic_load_n(c->h_flag, __ATOMIC_ACQUIRE) == want) break;
-    if ((i & 4095) == 0) {
+    if ((i & 255) == 0 && clk::now() >= next_check) {
       const hipError_t e = hipStreamQuery(c->stream);
       if (e == hipSuccess) {
         if (__atomic_load_n(c->h_flag, __ATOMIC_ACQUIRE) == want) break;
@@ -1635,6 +1665,7 @@ int rta_process(rta_ctx* c, const float* in, float* out) {
         return RTA_E_DEVICE;
       }
       if (e != hipErrorNotReady) HIP_TRY(c, e);
+      next_check = clk::now() + std::chrono::milliseconds(1);
     }
   }
   std::memcpy(out, c->h_out, sizeof(float) * (size_t)c->L * c->B);
@@ -1722,9 +1753,11 @@ int rta_set_feedback(rta_ctx* c, const float* const* fb, const int64_t* lengths,
   return zero_state(c);
 }
 
-int rta_timing_enable(rta_ctx* c, int32_t on) {
-  if (c == nullptr) return RTA_E_ARG;
-  c->timing = on != 0;
+int rta_timing_enable(rta_ctx* c, int32_t every) {
+  if (c == nullptr || every < 0) return RTA_E_ARG;
+  if (every > 0) c->timing_span_read = every;  // spans recorded from now on
+  c->timing = every;
+  c->span_open = false;
   return RTA_OK;
 }
 
@@ -1738,9 +1771,10 @@ int rta_timing_read(rta_ctx* c, int64_t* blocks, double* block_ms) {
     HIP_TRY(c, hipEventSynchronize(c->events[i + 1]));
     HIP_TRY(c, hipEventElapsedTime(&ms, c->events[i], c->events[i + 1]));
     *block_ms += ms;
-    *blocks += 1;
+    *blocks += std::max(1, c->timing_span_read);
   }
   c->events_used = 0;
+  c->span_open = false;
   return RTA_OK;
 }
 
@@ -1800,18 +1834,20 @@ int rta_autotune(double fs, int32_t block, const rta_scheme* scheme, int32_t n_i
   rta_tuning bt{};
   for (int g : {1, 2, 4}) {
     if (g > n_out) continue;
-    for (int items : {512, 1024, 2048}) {
-      rta_tuning tu{};
-      tu.outputs_per_group = g;
-      tu.tail_items = items;
-      double us = 0;
-      const int s2 = trial(schemes[best_s], tu, &us);
-      if (s2 == RTA_E_DEVICE) return s2;
-      if (s2 == RTA_OK && us < best_t) {
-        best_t = us;
-        bt = tu;
+    for (int items : {512, 1024, 2048})
+      for (int slices : {1, 2, 4}) {
+        rta_tuning tu{};
+        tu.outputs_per_group = g;
+        tu.tail_items = items;
+        tu.bin_slices = slices;
+        double us = 0;
+        const int s2 = trial(schemes[best_s], tu, &us);
+        if (s2 == RTA_E_DEVICE) return s2;
+        if (s2 == RTA_OK && us < best_t) {
+          best_t = us;
+          bt = tu;
+        }
       }
-    }
   }
   bt.n_tiers = (int32_t)schemes[best_s].size();
   for (int t = 0; t < bt.n_tiers; ++t) {

@@ -86,6 +86,7 @@ class rta_tuning(ctypes.Structure):
                 ("tail_items", ctypes.c_int32),
                 ("tail_rows", ctypes.c_int32),
                 ("tier_rows", ctypes.c_int32),
+                ("bin_slices", ctypes.c_int32),
                 ("n_tiers", ctypes.c_int32),
                 ("size", ctypes.c_int32 * RTA_MAX_TIERS),
                 ("count", ctypes.c_int32 * RTA_MAX_TIERS)]
@@ -205,10 +206,11 @@ def _marshal(filters, n_in, n_out, lengths, scheme):
     return keep, ptrs, lens, sch
 
 
-def make_tuning(outputs_per_group=0, tail_items=0, tail_rows=0, tier_rows=0) -> rta_tuning:
+def make_tuning(outputs_per_group=0, tail_items=0, tail_rows=0, tier_rows=0,
+                bin_slices=0) -> rta_tuning:
     t = rta_tuning()
     t.outputs_per_group, t.tail_items = outputs_per_group, tail_items
-    t.tail_rows, t.tier_rows = tail_rows, tier_rows
+    t.tail_rows, t.tier_rows, t.bin_slices = tail_rows, tier_rows, bin_slices
     return t
 
 
@@ -296,8 +298,10 @@ def rta_query(ctx) -> dict:
     return d
 
 
-def rta_timing_enable(ctx, on: bool) -> None:
-    _check(_lib.rta_timing_enable(ctx, 1 if on else 0), "rta_timing_enable")
+def rta_timing_enable(ctx, every) -> None:
+    """every: record kernel events on every `every`-th block (True = 1,
+    False/0 = off)."""
+    _check(_lib.rta_timing_enable(ctx, int(every)), "rta_timing_enable")
 
 
 def rta_timing_read(ctx):

@@ -90,6 +90,27 @@ def test_upols_fp32_matches_oracle_full_length(rta, case, G):
     check_db(y, ref, FP32_DB, f"B={B} G={G}")
 
 
+@pytest.mark.parametrize("S", [2, 4, 8])
+@pytest.mark.parametrize("case", [3, 4, 5, 6, 7])
+def test_bin_sliced_items_match_oracle(rta, case, S):
+    """First-tier items covering 1/S of each row's bins (more rows each, fewer
+    partial slots per output group)."""
+    B, lens, nb = CASES[case]
+    Q, L = len(lens), len(lens[0])
+    filt = make_filters(case + 1, lens)
+    maxlen = max(max(r) for r in lens)
+    x = padded_signal(case + 50, Q, nb, B, maxlen)
+    say(f"case {case}: B={B} lens={lens} bin slices {S}")
+    tun = rta.make_tuning(outputs_per_group=2, tail_rows=5, bin_slices=S)
+    with rta.Convolver(filt, B, tuning=tun) as cv:
+        y = cv.run(x)
+        cv.reset()
+        y2 = cv.run_device(x)
+    assert np.array_equal(y, y2)
+    ref = oracle.direct(x, filt, 0, x.shape[1])
+    check_db(y, ref, FP32_DB, f"B={B} S={S}")
+
+
 def test_device_path_equals_host_path_and_reruns_are_bitwise(rta):
     B, lens, nb = CASES[5]
     filt = make_filters(77, lens)
@@ -216,3 +237,24 @@ def test_autotune_returns_a_tuning_that_matches_the_oracle(rta):
         y = cv.run(x)
     ref = oracle.fftols(x, filt, x.shape[1])
     check_db(y, ref, FP32_DB, "autotuned")
+
+
+def test_block_timing_spans(rta):
+    """rta_timing_enable(every): spans of `every` blocks starting at multiples
+    of it; only complete spans are returned."""
+    filt = make_filters(5, [[600, 100]])
+    x = workloads.white_noise(6, 1, 64 * 40)
+    with rta.Convolver(filt, 64) as cv:
+        rta.rta_timing_enable(cv.ctx, 4)
+        for b in range(18):                # spans 0-3, 4-7, 8-11, 12-15; 16-17 open
+            cv.process(x[:, b * 64:(b + 1) * 64])
+        n, ms = rta.rta_timing_read(cv.ctx)
+        assert n == 16 and ms > 0.0
+        rta.rta_timing_enable(cv.ctx, 1)   # block 18, 19, 20: one span each
+        for b in range(18, 21):
+            cv.process(x[:, b * 64:(b + 1) * 64])
+        n, ms = rta.rta_timing_read(cv.ctx)
+        assert n == 3 and ms > 0.0
+        rta.rta_timing_enable(cv.ctx, 0)
+        cv.process(x[:, 21 * 64:22 * 64])
+        assert rta.rta_timing_read(cv.ctx) == (0, 0.0)
