@@ -59,7 +59,7 @@ struct Item {          // one workgroup's work in one block (48 bytes)
   int32_t p0, p1;      // partition range
   int32_t k0;          // first bin of the slice
   int32_t slot;        // partial-sum slot (tier-local)
-  int32_t target;      // items of this group launched in this block
+  int32_t acc;         // K_MAC of a later tier: add to the slot (0: store)
   int32_t lag;         // tiers >= 1: launch index minus the block in which
                        // the frame's input completed
   int32_t pad;
@@ -291,12 +291,17 @@ __device__ void mac_item(const KArgs& A, const DevTier& T, const Item& it,
         res[g][j] = make_float2(acc[g][j][0] - acc[g][j][1], acc[g][j][2] + acc[g][j][3]);
     }
 
+  // later tiers: chunks of one (group, input) accumulated in earlier blocks
+  // of the frame share the slot; the first stored it
   float2* part = T.partial + (int64_t)it.slot * G * P;
   if (RP == 1) {
 #pragma unroll
     for (int g = 0; g < G; ++g)
 #pragma unroll
-      for (int j = 0; j < C; ++j) part[(int64_t)g * P + kb + j] = res[g][j];
+      for (int j = 0; j < C; ++j) {
+        float2* d = part + (int64_t)g * P + kb + j;
+        *d = it.acc ? cadd(*d, res[g][j]) : res[g][j];
+      }
     return;
   }
 #pragma unroll
@@ -308,7 +313,8 @@ __device__ void mac_item(const KArgs& A, const DevTier& T, const Item& it,
     const int g = e / W, b = e - g * W;
     float2 sum = red[g * W + b];
     for (int s2 = 1; s2 < RP; ++s2) sum = cadd(sum, red[(s2 * G + g) * W + b]);
-    part[(int64_t)g * P + it.k0 + b] = sum;
+    float2* d = part + (int64_t)g * P + it.k0 + b;
+    *d = it.acc ? cadd(*d, sum) : sum;
   }
 }
 
@@ -760,10 +766,11 @@ __global__ __launch_bounds__(kThreads) void k_tier(const KArgs A) {
     return;
   }
 
-  // K_FINAL: one output group of frame f
+  // K_FINAL: output k0 of its group, frame f
   const Group grp = A.groups[it.group];
   const float scale = 1.0f / (float)(2 * P);
-  for (int g = 0; g < grp.nl; ++g) {
+  {
+    const int g = it.k0;
     const int l = grp.l0 + g;
     Group tg = grp;  // this tier's partial slots of the group
     tg.slot0 = A.tier_slot0[(int64_t)it.tier * A.n_groups_total + it.group];

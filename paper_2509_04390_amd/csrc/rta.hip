@@ -493,47 +493,99 @@ int build_plan(rta_ctx* c, Plan& plan) {
     const int nmac = tier_nmac(c, t);
     if (nmac < 1) return RTA_E_STATE;
     const int R = std::max(1, c->tier_rows);
-    struct Chunk { int g, q, p0, p1, slot, cap; };
+    struct Chunk { int g, q, p0, p1, slot, cap, acc; };
     std::vector<Chunk> chunks;
     const int nch_cap = fixed ? (T.kcap + R - 1) / R : 0;
-    int slot = 0;
-    for (int g = 0; g < ngroups; ++g) {
-      const Group& gr = plan.groups[g];
-      plan.tier_slot0[(size_t)t * ngroups + g] = slot;
-      const int gslot0 = slot;
-      if (fixed) slot += c->Q * nch_cap;
+    for (int g = 0; g < ngroups; ++g)
       for (int q = 0; q < c->Q; ++q) {
-        const int kg = group_rows(T, gr, q);
+        const int kg = group_rows(T, plan.groups[g], q);
         if (kg == 0) continue;
         const int nch = (kg + R - 1) / R;
         for (int ch = 0; ch < nch; ++ch) {
           if (fixed)
-            chunks.push_back(Chunk{g, q, ch * R, std::min(kg, (ch + 1) * R), gslot0 + q * nch_cap + ch,
-                                   (g * c->Q + q) * nch_cap + ch});
+            chunks.push_back(Chunk{g, q, ch * R, std::min(kg, (ch + 1) * R), 0,
+                                   (g * c->Q + q) * nch_cap + ch, 0});
           else
             chunks.push_back(Chunk{g, q, (int)((int64_t)ch * kg / nch),
-                                   (int)((int64_t)(ch + 1) * kg / nch), slot++, 0});
+                                   (int)((int64_t)(ch + 1) * kg / nch), 0, 0, 0});
         }
       }
-      plan.tier_nslot[(size_t)t * ngroups + g] = slot - plan.tier_slot0[(size_t)t * ngroups + g];
-    }
-    T.nslots = slot;
-    // spread the chunks over the nmac blocks, balancing rows; with the fixed
-    // serving layout a chunk's block depends on its slot alone, so a frame
-    // whose accumulation straddles a work-list switch still writes every
-    // slot exactly once
+    // spread the chunks over the nmac blocks, balancing rows (the block of a
+    // chunk never decreases along a (group, input)'s partitions); with the
+    // fixed serving layout a chunk's block depends on its capacity index
+    // alone, so work lists of any set of sources agree on it
     int64_t total = 0;
     for (const Chunk& ch : chunks) total += ch.p1 - ch.p0;
     std::vector<int> when(chunks.size(), 0);
     int64_t acc = 0;
     const int64_t ncap = (int64_t)ngroups * c->Q * nch_cap;
+    auto cap_when = [&](int64_t cap) {
+      return (int)std::min<int64_t>(nmac - 1, cap * nmac / std::max<int64_t>(1, ncap));
+    };
     for (size_t i = 0; i < chunks.size(); ++i) {
-      if (fixed)
-        when[i] = (int)std::min<int64_t>(nmac - 1, (int64_t)chunks[i].cap * nmac / std::max<int64_t>(1, ncap));
-      else
-        when[i] = total > 0 ? (int)std::min<int64_t>(nmac - 1, acc * nmac / total) : 0;
+      when[i] = fixed ? cap_when(chunks[i].cap)
+                      : (total > 0 ? (int)std::min<int64_t>(nmac - 1, acc * nmac / total) : 0);
       acc += chunks[i].p1 - chunks[i].p0;
     }
+    // partial slots: chunks of one (group, input) accumulated in different
+    // blocks share a slot -- the first in frame order stores, the later ones
+    // add -- so a group owns only as many slots per input as it has chunks in
+    // one block, and its final step has that few to reduce.  rank = chunks of
+    // the same (group, input) and block before this one.
+    // for a (group, input)'s chunks in partition order (blocks w[] non-
+    // decreasing): rank[ch] within its block, acc[ch] = an earlier block had
+    // a chunk of the same rank; returns the slots needed
+    auto rank_chunks = [](const std::vector<int>& w, std::vector<int>& rank, std::vector<int>& accf) {
+      const int n = (int)w.size();
+      rank.assign(n, 0);
+      accf.assign(n, 0);
+      int before = 0, in_block = 0, slots = 0;  // widest earlier block, this block so far
+      for (int ch = 0; ch < n; ++ch) {
+        if (ch > 0 && w[ch] != w[ch - 1]) {
+          before = std::max(before, in_block);
+          in_block = 0;
+        }
+        rank[ch] = in_block++;
+        accf[ch] = rank[ch] < before ? 1 : 0;
+        slots = std::max(slots, rank[ch] + 1);
+      }
+      return slots;
+    };
+    std::vector<int> wcap, rk, af;
+    int nsl_cap = 0;
+    if (fixed)  // a present source's chunks are a prefix of the capacity chunks
+      for (int g = 0; g < ngroups; ++g)
+        for (int q = 0; q < c->Q; ++q) {
+          wcap.assign(nch_cap, 0);
+          for (int ch = 0; ch < nch_cap; ++ch) wcap[ch] = cap_when((int64_t)(g * c->Q + q) * nch_cap + ch);
+          nsl_cap = std::max(nsl_cap, rank_chunks(wcap, rk, af));
+        }
+    int slot = 0;
+    size_t i0 = 0;
+    for (int g = 0; g < ngroups; ++g) {
+      plan.tier_slot0[(size_t)t * ngroups + g] = slot;
+      const int gslot0 = slot;
+      if (fixed) slot += c->Q * nsl_cap;
+      for (int q = 0; q < c->Q; ++q) {
+        size_t i1 = i0;
+        while (i1 < chunks.size() && chunks[i1].g == g && chunks[i1].q == q) ++i1;
+        std::vector<int> w(when.begin() + i0, when.begin() + i1);
+        if (fixed) {
+          wcap.assign(nch_cap, 0);
+          for (int ch = 0; ch < nch_cap; ++ch) wcap[ch] = cap_when((int64_t)(g * c->Q + q) * nch_cap + ch);
+        }
+        const int nsl = rank_chunks(fixed ? wcap : w, rk, af);
+        for (size_t i = i0; i < i1; ++i) {
+          const int ch = (int)(i - i0);
+          chunks[i].acc = af[ch];
+          chunks[i].slot = fixed ? gslot0 + q * nsl_cap + rk[ch] : slot + rk[ch];
+        }
+        if (!fixed) slot += nsl;
+        i0 = i1;
+      }
+      plan.tier_nslot[(size_t)t * ngroups + g] = slot - plan.tier_slot0[(size_t)t * ngroups + g];
+    }
+    T.nslots = slot;
     for (int ph0 = r - 1; ph0 < n_phase; ph0 += r) {  // phases in which a frame completes
       for (int q = 0; q < c->Q; ++q) {
         bool used = false;
@@ -559,6 +611,7 @@ int build_plan(rta_ctx* c, Plan& plan) {
           it.k0 = sl * W;
           it.w = W;
           it.slot = chunks[i].slot;
+          it.acc = chunks[i].acc;
           it.lag = lag;
           tier_mac[(ph0 + lag) % n_phase].push_back(it);
         }
@@ -566,12 +619,15 @@ int build_plan(rta_ctx* c, Plan& plan) {
       for (int g = 0; g < ngroups; ++g) {
         if (plan.tier_nslot[(size_t)t * ngroups + g] == 0) continue;
         if (fixed && chunks.empty()) continue;  // no source present
-        Item it{};
-        it.kind = K_FINAL;
-        it.tier = t;
-        it.group = g;
-        it.lag = nmac;
-        plan.tier[(ph0 + nmac) % n_phase].push_back(it);
+        for (int gi = 0; gi < plan.groups[g].nl; ++gi) {  // one per output
+          Item it{};
+          it.kind = K_FINAL;
+          it.tier = t;
+          it.group = g;
+          it.k0 = gi;
+          it.lag = nmac;
+          plan.tier[(ph0 + nmac) % n_phase].push_back(it);
+        }
       }
     }
   }
@@ -620,7 +676,9 @@ int build_plan(rta_ctx* c, Plan& plan) {
     for (const Item& it : plan.tier[ph]) {
       if (it.tier < 1 || it.tier >= c->n_tiers) return RTA_E_STATE;
       if (it.kind == K_FFT && (it.q < 0 || it.q >= c->Q || it.lag != 0)) return RTA_E_STATE;
-      if (it.kind == K_FINAL && (it.group < 0 || it.group >= ngroups || it.lag < 1)) return RTA_E_STATE;
+      if (it.kind == K_FINAL && (it.group < 0 || it.group >= ngroups || it.lag < 1 || it.k0 < 0 ||
+                                 it.k0 >= plan.groups[it.group].nl))
+        return RTA_E_STATE;
       if (it.kind != K_FFT && it.kind != K_FINAL) return RTA_E_STATE;
     }
   }
