@@ -84,6 +84,24 @@ struct DevTier {
   int32_t pad2;
 };
 
+// Feedback convolution fused into the synthesis launch (Sec. III-A Eq. 3,
+// Sec. V).  Its inputs are the synthesis outputs y_l, its outputs the
+// estimates c_q that the next block subtracts from the microphones.
+struct FcArgs {
+  DevTier T;                 // its single tier (uniform partitions, P = B)
+  const Item* items;         // its multiply-accumulate items (terms p >= 2)
+  const Group* groups;       // its output groups (partial-slot layout)
+  const void* H01;           // [Lf][Qf][2][P] its partitions 0 and 1
+  float* hist;               // [Qf][hist_len] synthesis output history
+  float* c;                  // [Lf][B] estimate c_{n-1}, written by its heads
+  unsigned int* done;        // its heads done so far (monotonic, system scope)
+  int64_t hist_mask;
+  int32_t n_items;           // its items per launch
+  int32_t tail0;             // tail index of its first item in the launch
+  int32_t n_heads, head_slots;  // one head per feedback output; part of the grid
+  int32_t Qf, Lf;            // its inputs (= synthesis outputs), outputs
+};
+
 struct KArgs {
   DevTier tier[kMaxTiers];
   const Item* items;         // [n_phase][max_items]
@@ -114,6 +132,9 @@ struct KArgs {
   float* out2;               // second copy of the output block (feedback input)
   const int32_t* live;       // [Q] serving: 0 = the slot's input reads as zero
                              // (null: every input is live)
+  int32_t fc_on;             // the feedback convolution runs in this launch
+  int32_t pad3;
+  FcArgs fc;
 };
 
 // ---------------------------------------------------------------------------
@@ -195,7 +216,7 @@ __device__ __forceinline__ int wrap_slot(int64_t v, int K) {
 // p pairs with slot (frame - p) mod K).
 // ---------------------------------------------------------------------------
 template <typename HT, int G>
-__device__ void mac_item(const KArgs& A, const DevTier& T, const Item& it,
+__device__ void mac_item(int Qn, const DevTier& T, const Item& it,
                          const Group& grp, int64_t frame, float2* red) {
   constexpr int C = HVec<HT>::C;
   const int P = T.P;
@@ -215,7 +236,7 @@ __device__ void mac_item(const KArgs& A, const DevTier& T, const Item& it,
     pend[g] = 0;
     hb[g] = Hbase;
     if (g < grp.nl) {
-      const int pair = (grp.l0 + g) * A.Q + q;
+      const int pair = (grp.l0 + g) * Qn + q;
       const int64_t row = T.pair_row[pair];
       if (row >= 0) {
         pend[g] = min(it.p1, T.pair_K[pair]);
@@ -483,9 +504,17 @@ __device__ void head_work(const KArgs& A, const Group& grp, int gsel, float2* ld
   const int ept = (E + kThreads - 1) / kThreads;       // output elements per thread
   const int half = P >> 1;
   const int eo = grp.nl * half;                         // output sample pairs
-  const bool pre_w = nb0 * P <= WMAX * kThreads;
+  // (fused feedback: the window needs c_{n-1}, which this launch's feedback
+  // heads are still computing, so it is not prefetched)
+  const bool pre_w = nb0 * P <= WMAX * kThreads && !A.fc_on;
   const bool pre_h = ept * nb0 <= HMAX;
   const bool pre_r = A.n_tiers - 1 <= TMAX && eo <= RMAX * kThreads;
+  // feedback estimate sample i of input q (fused: written in this launch by
+  // another workgroup, so read where every XCD sees it)
+  auto sub_at = [&](int q, int i) {
+    const float* p = A.sub + (int64_t)q * A.B + i;
+    return A.fc_on ? __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) : *p;
+  };
   auto window = [&](int e, int q0) {
     const int b = e / P, m = e - b * P;
     const int q = q0 + b;
@@ -497,9 +526,8 @@ __device__ void head_work(const KArgs& A, const Group& grp, int gsel, float2* ld
       w0 = i0 < P ? hq[((n - 1) * A.B + i0) & A.hist_mask] : iq[i0 - P];
       w1 = i1 < P ? hq[((n - 1) * A.B + i1) & A.hist_mask] : iq[i1 - P];
     } else {  // microphone minus the previous block's feedback estimate
-      const float* sq = A.sub + (int64_t)q * A.B;
-      w0 = i0 < P ? hq[((n - 1) * A.B + i0) & A.hist_mask] : iq[i0 - P] - sq[i0 - P];
-      w1 = i1 < P ? hq[((n - 1) * A.B + i1) & A.hist_mask] : iq[i1 - P] - sq[i1 - P];
+      w0 = i0 < P ? hq[((n - 1) * A.B + i0) & A.hist_mask] : iq[i0 - P] - sub_at(q, i0 - P);
+      w1 = i1 < P ? hq[((n - 1) * A.B + i1) & A.hist_mask] : iq[i1 - P] - sub_at(q, i1 - P);
     }
     if (A.live != nullptr && A.live[q] == 0) {  // a select, so NaN input stays out
       if (i0 >= P) w0 = 0.f;
@@ -553,6 +581,21 @@ __device__ void head_work(const KArgs& A, const Group& grp, int gsel, float2* ld
   }();
   head_reduce<HT, G>(A, Tcur, grp, n, Y, scratch);
 
+  // fused feedback: wait until every feedback head of this launch has
+  // published c_{n-1} (they are dispatched first and wait for nothing; the
+  // spin is bounded all the same)
+  if (A.fc_on) {
+    if (tid == 0) {
+      const unsigned int target = (unsigned int)((n + 1) * A.fc.n_heads);
+      for (int it = 0; it < (1 << 24); ++it) {
+        if ((int)(__hip_atomic_load(A.fc.done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) - target) >= 0)
+          break;
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    __syncthreads();
+  }
+
   // 2. the term p = 0: window -> real FFT -> ring slot n mod K, times H_{l,q,0}
   const int slot0 = wrap_slot(n, T.K);
   for (int q0 = 0; q0 < A.Q; q0 += A.head_nq) {
@@ -578,7 +621,7 @@ __device__ void head_work(const KArgs& A, const Group& grp, int gsel, float2* ld
       for (int e = tid; e < nb * A.B; e += kThreads) {
         const int b = e / A.B, i = e - b * A.B;
         const int q = q0 + b;
-        const float v = A.in[(int64_t)q * A.B + i] - (A.sub ? A.sub[(int64_t)q * A.B + i] : 0.f);
+        const float v = A.in[(int64_t)q * A.B + i] - (A.sub ? sub_at(q, i) : 0.f);
         A.hist[(int64_t)q * (A.hist_mask + 1) + ((n * A.B + i) & A.hist_mask)] =
             (A.live != nullptr && A.live[q] == 0) ? 0.f : v;
       }
@@ -630,6 +673,10 @@ __device__ void head_work(const KArgs& A, const Group& grp, int gsel, float2* ld
       A.out2[(int64_t)l * A.B + i] = o0;
       A.out2[(int64_t)l * A.B + i + 1] = o1;
     }
+    if (A.fc_on) {  // kept for the feedback hand-off (one output per head)
+      reinterpret_cast<float*>(Y)[i] = o0;
+      reinterpret_cast<float*>(Y)[i + 1] = o1;
+    }
   };
   auto clear_rings = [&](int e) {
     const int g = e / half, j = 2 * (e - g * half);
@@ -672,23 +719,130 @@ __device__ void head_work(const KArgs& A, const Group& grp, int gsel, float2* ld
   // 4. completion (rta_process only): every head makes its output visible
   //    system-wide, the last one raises the flag (only the heads count, so
   //    the host does not wait for the tail workgroups of this launch)
-  if (A.done_flag == nullptr) return;
-  __threadfence_system();
-  __syncthreads();
-  if (tid == 0) {
-    const unsigned int old = __hip_atomic_fetch_add(A.head_count, 1u, __ATOMIC_ACQ_REL,
-                                                    __HIP_MEMORY_SCOPE_SYSTEM);
-    if (old == (unsigned int)A.n_head - 1u) {
-      __hip_atomic_store(A.head_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(A.done_flag, n + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  if (A.done_flag != nullptr) {
+    __threadfence_system();
+    __syncthreads();
+    if (tid == 0) {
+      const unsigned int old = __hip_atomic_fetch_add(A.head_count, 1u, __ATOMIC_ACQ_REL,
+                                                      __HIP_MEMORY_SCOPE_SYSTEM);
+      if (old == (unsigned int)A.n_head - 1u) {
+        __hip_atomic_store(A.head_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(A.done_flag, n + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
     }
   }
+
+  // 5. fused feedback: this output is input l of the feedback convolution;
+  //    its window [y_l(n-1), y_l(n)] is transformed here, where y_l(n) already
+  //    is, into the feedback delay line (slot n), and y_l(n) goes to its
+  //    history -- the feedback launch needs no transform of its own
+  if (!A.fc_on) return;
+  __syncthreads();
+  {
+    const FcArgs& F = A.fc;
+    const int l = grp.l0;
+    const float* yn = reinterpret_cast<const float*>(Y);
+    float* hl = F.hist + (int64_t)l * (F.hist_mask + 1);
+    for (int m = tid; m < P; m += kThreads) {
+      const int i0 = 2 * m, i1 = 2 * m + 1;
+      const float w0 = i0 < P ? hl[((n - 1) * A.B + i0) & F.hist_mask] : yn[i0 - P];
+      const float w1 = i1 < P ? hl[((n - 1) * A.B + i1) & F.hist_mask] : yn[i1 - P];
+      Xa[m] = make_float2(w0, w1);
+    }
+    __syncthreads();
+    for (int i = tid; i < A.B; i += kThreads) hl[(n * A.B + i) & F.hist_mask] = yn[i];
+    float2* zf = fft_stockham<false>(Xa, Xb, P, logP, tw);
+    float2* xf = (zf == Xa) ? Xb : Xa;
+    rfft_post(zf, xf, P, tw + P);
+    float2* dst = F.T.X + ((int64_t)l * F.T.K + wrap_slot(n, F.T.K)) * P;
+    for (int k = tid; k < P; k += kThreads) dst[k] = xf[k];
+  }
+}
+
+// Feedback head of the fused launch n: output j of the feedback convolution
+// for block n - 1, c_j = IFFT(sum of its partial slots (its items of launch
+// n - 1) + sum_l F_{j,l,1} Y'_l(n-2) + F_{j,l,0} Y'_l(n-1)), the second half
+// of the 2B samples; then it counts itself done (system scope, after making
+// c visible).  Y' are the synthesis heads' transforms of their outputs.
+template <typename HT, int G>
+__device__ void fc_head_work(const KArgs& A, int j, float2* lds) {
+  const FcArgs& F = A.fc;
+  const DevTier& T = F.T;
+  const int P = T.P, logP = T.logP, tid = threadIdx.x;
+  const int64_t n = A.n;
+  const Group g0 = F.groups[j / G];
+  const int gsel = j - g0.l0;
+  float2* Y = lds;
+  float2* Xa = lds + P;
+  float2* Xb = lds + 2 * P;
+  float2* scratch = lds + 3 * P + tw_lds_len(P);
+  const float2* tw = stage_twiddles(T, lds + 3 * P);
+  const HT* H01 = reinterpret_cast<const HT*>(F.H01);
+  const int64_t stride = (int64_t)G * P;
+  const float2* base = T.partial + ((n - 1) & 1) * (int64_t)T.nslots * G * P +
+                       (int64_t)g0.slot0 * stride + (int64_t)gsel * P;
+  const int s1 = wrap_slot(n - 1, T.K), s2 = wrap_slot(n - 2, T.K);
+  auto term = [&](int k, int q0, int dq) {
+    float2 acc = make_float2(0.f, 0.f);
+#pragma unroll 4
+    for (int q = q0; q < F.Qf; q += dq) {
+      const HT* hr = H01 + ((int64_t)(j * F.Qf + q) * 2) * P + k;
+      const float2 h0 = HVec<HT>::load1(hr), h1 = HVec<HT>::load1(hr + P);
+      const float2 x0 = T.X[((int64_t)q * T.K + s1) * P + k];
+      const float2 x1 = T.X[((int64_t)q * T.K + s2) * P + k];
+      if (k == 0)
+        acc = cadd(acc, make_float2(h0.x * x0.x + h1.x * x1.x, h0.y * x0.y + h1.y * x1.y));
+      else
+        acc = cadd(acc, cadd(cmul(h0, x0), cmul(h1, x1)));
+    }
+    return acc;
+  };
+  // threads split into 256 / P groups (at least one) over bins and inputs
+  const int ng = P >= kThreads ? 1 : kThreads / P;
+  const int tg = tid / (P >= kThreads ? kThreads : P);
+  for (int k = tid % (P >= kThreads ? kThreads : P); k < P; k += (P >= kThreads ? kThreads : P)) {
+    float2 acc = term(k, tg, ng);
+    const int per = (g0.nslot + ng - 1) / ng;
+    const int a0 = min(g0.nslot, tg * per), a1 = min(g0.nslot, a0 + per);
+#pragma unroll 8
+    for (int sl = a0; sl < a1; ++sl) acc = cadd(acc, base[sl * stride + k]);
+    if (ng == 1) Y[k] = acc; else scratch[tid] = acc;
+  }
+  __syncthreads();
+  if (ng > 1) {
+    if (tid < P) {
+      float2 t = scratch[tid];
+      for (int g2 = 1; g2 < ng; ++g2) t = cadd(t, scratch[g2 * P + tid]);
+      Y[tid] = t;
+    }
+    __syncthreads();
+  }
+  irfft_pre(Y, Xa, P, tw + P);
+  float2* z = fft_stockham<true>(Xa, Xb, P, logP, tw);
+  const float scale = 1.0f / (float)(2 * P);
+  const int half = P >> 1;
+  float* cj = F.c + (int64_t)j * A.B;
+  for (int m = half + tid; m < P; m += kThreads) {
+    const int i = 2 * (m - half);
+    __hip_atomic_store(cj + i, z[m].x * scale, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(cj + i + 1, z[m].y * scale, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+  __threadfence_system();
+  __syncthreads();
+  if (tid == 0) __hip_atomic_fetch_add(F.done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 template <typename HT, int G>
 __global__ __launch_bounds__(kThreads) void k_block(const KArgs A) {
   extern __shared__ float2 lds[];
-  const int b = blockIdx.x;
+  int b = blockIdx.x;
+  if (A.fc_on) {  // grid: feedback heads | heads | tails | feedback tails
+    if (b < A.fc.head_slots) {
+      if (b < A.fc.n_heads) fc_head_work<HT, G>(A, b, lds);
+      return;
+    }
+    b -= A.fc.head_slots;
+  }
   if (b < A.head_slots) {
     if (b < A.n_head) {  // head b: output b, in group b / G
       const Group g0 = A.groups[b / G];
@@ -701,6 +855,16 @@ __global__ __launch_bounds__(kThreads) void k_block(const KArgs A) {
   }
   const int phase = (int)(A.n % A.n_phase);
   const int i = b - A.head_slots;
+  if (A.fc_on && i >= A.fc.tail0) {  // feedback terms p >= 2 for c_n
+    const int j = i - A.fc.tail0;
+    if (j >= A.fc.n_items) return;
+    const Item it = A.fc.items[j];
+    if (it.kind == K_NOP) return;
+    DevTier T = A.fc.T;
+    T.partial += (A.n & 1) * (int64_t)T.nslots * G * T.P;
+    mac_item<HT, G>(A.fc.Qf, T, it, A.fc.groups[it.group], A.n, lds);
+    return;
+  }
   if (i >= A.phase_count[phase]) return;
   const Item it = A.items[(int64_t)phase * A.max_items + i];
   if (it.kind == K_NOP) return;
@@ -713,7 +877,7 @@ __global__ __launch_bounds__(kThreads) void k_block(const KArgs A) {
     // later tier: the frame whose input completed in block n - lag
     frame = (A.n - it.lag + 1) / T.r - 1;
   }
-  mac_item<HT, G>(A, T, it, A.groups[it.group], frame, lds);
+  mac_item<HT, G>(A.Q, T, it, A.groups[it.group], frame, lds);
 }
 
 // ---------------------------------------------------------------------------

@@ -81,6 +81,7 @@ struct rta_ctx {
   int n_groups = 0, head_slots = 0, head_nq = 1;
   int64_t hist_len = 0, ring_len = 0;
   size_t lds = 0;              // k_block dynamic LDS
+  size_t lds_fused = 0;        // with the feedback convolution in the launch
   int64_t block = 0;           // index of the next block
 
   void* H01 = nullptr;         // [L][Q][2][P] partitions 0 and 1
@@ -107,7 +108,11 @@ struct rta_ctx {
   rta_ctx* fc = nullptr;        // feedback convolution: outputs -> inputs
   float* d_y = nullptr;         // [L][B] copy of the output block (its input)
   float* d_c = nullptr;         // [Q][B] its output, subtracted next block
+  bool fc_fused = false;        // it runs inside this context's launch
+  unsigned int* fc_done = nullptr;  // its heads done (fused; monotonic)
+  int min_ring = 1;             // first tier's delay line has at least this many slots
 
+  std::vector<int32_t> block_count_host;  // k_block items per phase (active list)
   const int32_t* live = nullptr;  // serving: [Q] live mask of the active list
   int grid_items = 0;             // tail part of the grid
   Serve* serve = nullptr;         // serving state (rta_serve_create)
@@ -141,7 +146,7 @@ struct PlanDev {  // one of the two work-list buffers
   int64_t* pair_row[kMaxTiers] = {};
   int32_t* pair_K[kMaxTiers] = {};
   int32_t* live = nullptr;
-  std::vector<int32_t> tier_count_host;
+  std::vector<int32_t> tier_count_host, block_count_host;
   int grid_items = 0;
   double hb = 0, xb = 0, cm = 0, tb = 0;
 };
@@ -732,6 +737,39 @@ KArgs make_args(const rta_ctx* c, const float* in, float* out, int64_t n) {
   a.max_tier_items = c->max_tier_items;
   a.n_groups_total = c->n_groups;
   a.live = c->live;
+  if (c->fc != nullptr && c->fc_fused) {
+    const rta_ctx* f = c->fc;
+    const TierHost& T = f->tier[0];
+    FcArgs& F = a.fc;
+    F.T.H = T.H;
+    F.T.pair_row = T.pair_row;
+    F.T.pair_K = T.pair_K;
+    F.T.X = T.X;
+    F.T.partial = T.partial;
+    F.T.tw = T.tw;
+    F.T.oring = nullptr;
+    F.T.offset = 0;
+    F.T.P = T.P;
+    F.T.logP = T.logP;
+    F.T.K = T.K;
+    F.T.nslots = std::max(1, T.nslots);
+    F.T.r = 1;
+    F.items = f->items;
+    F.groups = f->groups;
+    F.H01 = f->H01;
+    F.hist = f->hist;
+    F.c = c->d_c;
+    F.done = c->fc_done;
+    F.hist_mask = f->hist_len - 1;
+    F.n_items = f->block_count_host.empty() ? 0 : f->block_count_host[0];
+    F.tail0 = c->grid_items;
+    F.n_heads = f->L;
+    F.head_slots = (f->L + kXcds - 1) / kXcds * kXcds;
+    F.Qf = f->Q;
+    F.Lf = f->L;
+    a.fc_on = 1;
+    a.sub = c->d_c;
+  }
   return a;
 }
 
@@ -742,6 +780,7 @@ void activate(rta_ctx* c, const PlanDev& d) {
   c->tier_items = d.tier_items;
   c->tier_count = d.tier_count;
   c->tier_count_host = d.tier_count_host;
+  c->block_count_host = d.block_count_host;
   for (int t = 0; t < c->n_tiers; ++t) {
     c->tier[t].pair_row = d.pair_row[t];
     c->tier[t].pair_K = d.pair_K[t];
@@ -814,7 +853,12 @@ int launch_block(rta_ctx* c, const float* in, float* out, hipStream_t s, bool fl
   }
   KArgs a = make_args(c, in, out, c->block);
   if (flag) a.done_flag = c->m_flag;
-  const unsigned grid = (unsigned)(c->head_slots + c->grid_items);
+  unsigned grid = (unsigned)(c->head_slots + c->grid_items);
+  size_t lds = c->lds;
+  if (a.fc_on) {
+    grid += (unsigned)(a.fc.head_slots + a.fc.n_items);
+    lds = c->lds_fused;
+  }
   const int phase = (int)(c->block % c->n_phase);
   const int n_tier = c->tier_count_host.empty() ? 0 : c->tier_count_host[phase];
   // timing: a span of `timing` consecutive blocks starts at every block
@@ -833,17 +877,19 @@ int launch_block(rta_ctx* c, const float* in, float* out, hipStream_t s, bool fl
     HIP_TRY(c, hipEventRecord(c->events[c->events_used], s));
     c->span_open = true;
   }
-  if (c->fc != nullptr) {
+  if (c->fc != nullptr && !c->fc_fused) {
     a.sub = c->d_c;
     a.out2 = c->d_y;
   }
-  hipLaunchKernelGGL(block_kernel(c->dtype, c->G), dim3(grid), dim3(kThreads), c->lds, s, a);
+  hipLaunchKernelGGL(block_kernel(c->dtype, c->G), dim3(grid), dim3(kThreads), lds, s, a);
   HIP_TRY(c, hipGetLastError());
   if (n_tier > 0) {
     hipLaunchKernelGGL(tier_kernel(c->G), dim3(n_tier), dim3(kThreads), c->lds_tier, s, a);
     HIP_TRY(c, hipGetLastError());
   }
-  if (c->fc != nullptr) {  // feedback estimate of this block, for the next one
+  if (c->fc != nullptr && c->fc_fused) {
+    c->fc->block += 1;  // ran inside this launch
+  } else if (c->fc != nullptr) {  // feedback estimate of this block, for the next one
     const int st = launch_block(c->fc, c->d_y, c->d_c, s);
     if (st != RTA_OK) {
       c->poisoned = true;
@@ -873,6 +919,7 @@ int zero_state(rta_ctx* c) {
   HIP_TRY(c, hipMemsetAsync(c->hist, 0, sizeof(float) * (size_t)c->Q * c->hist_len, c->stream));
   HIP_TRY(c, hipMemsetAsync(c->head_count, 0, sizeof(unsigned int), c->stream));
   if (c->d_c) HIP_TRY(c, hipMemsetAsync(c->d_c, 0, sizeof(float) * (size_t)c->Q * c->B, c->stream));
+  if (c->fc_done) HIP_TRY(c, hipMemsetAsync(c->fc_done, 0, sizeof(unsigned int), c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   if (c->fc) {
     const int st = zero_state(c->fc);
@@ -1022,6 +1069,7 @@ int upload_plan(rta_ctx* c, const Plan& plan, PlanDev& d, const std::vector<int3
   HIP_TRY(c, hipMemcpyAsync(d.live, live.data(), sizeof(int32_t) * live.size(), hipMemcpyHostToDevice, s));
   HIP_TRY(c, hipStreamSynchronize(s));
   d.tier_count_host = cnt_t;
+  d.block_count_host = cnt_b;
   d.grid_items = grid;
   return RTA_OK;
 }
@@ -1129,7 +1177,7 @@ int create_impl(rta_ctx* c, const std::vector<int>& size, const std::vector<int>
         }
       }
     T.count = count[t] > 0 ? count[t] : kmax;
-    T.K = std::max(1, kmax);
+    T.K = std::max(t == 0 ? c->min_ring : 1, kmax);
     off += (int64_t)T.count * T.P;
     if (sv != nullptr) {
       T.kcap = kmax;
@@ -1210,6 +1258,7 @@ int create_impl(rta_ctx* c, const std::vector<int>& size, const std::vector<int>
     cnt_t[ph] = (int32_t)plan.tier[ph].size();
   }
   c->tier_count_host = cnt_t;
+  c->block_count_host = cnt_b;
   if ((st = dev_alloc(c, &c->items, all_b.size())) != RTA_OK) return st;
   if ((st = dev_alloc(c, &c->phase_count, cnt_b.size())) != RTA_OK) return st;
   if ((st = dev_alloc(c, &c->tier_items, all_t.size())) != RTA_OK) return st;
@@ -1636,9 +1685,11 @@ bool tuning_ok(const rta_tuning* tuning) {
 int create_ctx(rta_ctx** out, double fs, int32_t block, const std::vector<int>& size,
                const std::vector<int>& count, int32_t n_in, int32_t n_out,
                const float* const* filters, const int64_t* lengths, int32_t spectra,
-               uint32_t flags, const rta_tuning* tuning, const rta_serve_config* cfg) {
+               uint32_t flags, const rta_tuning* tuning, const rta_serve_config* cfg,
+               int min_ring = 1) {
   rta_ctx* c = new (std::nothrow) rta_ctx();
   if (c == nullptr) return RTA_E_NOMEM;
+  c->min_ring = min_ring;
   c->fs = fs;
   c->B = block;
   c->Q = n_in;
@@ -1797,16 +1848,45 @@ int rta_set_feedback(rta_ctx* c, const float* const* fb, const int64_t* lengths,
         ft[(int64_t)l * c->Q + q] = fb[(int64_t)q * c->L + l];
         lt[(int64_t)l * c->Q + q] = lengths[(int64_t)q * c->L + l];
       }
+    // validated like rta_create's arguments (uniform partitions, P = B)
+    std::vector<int> size, count;
+    int st = validate(c->fs, c->B, nullptr, c->L, c->Q, ft.data(), lt.data(), spectra, 0, size, count);
+    if (st != RTA_OK) return st;
+    // same outputs per group as this context, so its items can run in this
+    // context's launch; at least 3 delay-line slots (this launch writes slot
+    // n while its heads read n-1 and n-2)
+    rta_tuning tu{};
+    tu.outputs_per_group = c->G;
+    // its one head per output reduces all of that output's partial slots on
+    // the synthesis heads' critical path: 512 items in 8 bin slices keep them
+    // to about 64 while its items stay as small as the synthesis tails'
+    tu.tail_items = 512;
+    tu.bin_slices = 8;
     rta_ctx* fc = nullptr;
-    const int st = rta_create_tuned(&fc, c->fs, c->B, nullptr, c->L, c->Q, ft.data(), lt.data(),
-                                    spectra, 0, nullptr);
+    st = create_ctx(&fc, c->fs, c->B, size, count, c->L, c->Q, ft.data(), lt.data(), spectra, 0, &tu,
+                    nullptr, 3);
     if (st != RTA_OK) return st;
     c->fc = fc;
     if (c->d_y == nullptr) {
       int s2;
       if ((s2 = dev_alloc(c, &c->d_y, (size_t)c->L * c->B)) != RTA_OK) return s2;
       if ((s2 = dev_alloc(c, &c->d_c, (size_t)c->Q * c->B)) != RTA_OK) return s2;
+      if ((s2 = dev_alloc(c, &c->fc_done, 1)) != RTA_OK) return s2;
     }
+    // fused when both store the same spectrum type and the launch's LDS fits
+    const int P = c->tier[0].P, C = vec_bins(c->dtype);
+    const size_t fc_head = sizeof(float2) * (size_t)(3 * P + tw_lds_len(P) + kThreads);
+    const size_t fc_tail = sizeof(float2) * (size_t)kThreads * C * c->G;
+    c->lds_fused = std::max(c->lds, std::max(fc_head, fc_tail));
+    int max_lds = 0;
+    HIP_TRY(c, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
+    c->fc_fused = fc->dtype == c->dtype && fc->G == c->G && fc->n_tiers == 1 && fc->tier[0].K >= 3 &&
+                  fc->tier[0].P == P && (int64_t)c->lds_fused + 64 <= (int64_t)max_lds;
+    if (c->fc_fused && c->lds_fused > 65536)
+      HIP_TRY(c, hipFuncSetAttribute(reinterpret_cast<const void*>(block_kernel(c->dtype, c->G)),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_fused));
+  } else {
+    c->fc_fused = false;
   }
   return zero_state(c);
 }

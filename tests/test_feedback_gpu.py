@@ -78,3 +78,46 @@ def test_feedback_removed_restores_plain_synthesis(rta):
         cv.set_feedback(None)
         y = cv.run(m)
     check_db(y, oracle.direct(m, h, 0, m.shape[1]), FP32_DB, "feedback removed")
+
+
+@pytest.mark.parametrize("fb_spectra,spectra_db", [("fp16", -60.0), ("bf16", -45.0)])
+def test_feedback_in_a_separate_launch(rta, fb_spectra, spectra_db):
+    """Feedback spectra of another storage type than the synthesis spectra: the
+    feedback convolution runs as its own launch after each block instead of
+    inside the synthesis launch.  The estimate c carries the storage type's
+    relative error; it reaches the output through m - c, so the bound is that
+    error scaled by rms(c) / rms(m - c) (both from the oracle)."""
+    B, P, L = 32, 2, 3
+    h = make_filters(50, [[2500, 900, 0], [700, 2200, 400]])
+    # weak paths: the bound below ignores the loop's own amplification of
+    # the estimate's rounding error, which grows with the loop gain
+    f = weak(make_filters(51, [[400, 250, 600], [0, 500, 150]]), 0.004)
+    m = workloads.white_noise(52, P, 50 * B)
+    with rta.Convolver(h, B) as cv:
+        cv.set_feedback(f, spectra=fb_spectra)
+        y = cv.run(m)
+    l_ref, c_ref, mt_ref = oracle.feedback_loop(m, h, f, B)
+    gain = np.sqrt(np.mean(c_ref ** 2, axis=1) / np.mean(mt_ref ** 2, axis=1)).max()
+    limit = spectra_db + 20.0 * np.log10(max(1.0, gain))
+    say(f"  |c| / |m - c| = {gain:.2f}: bound {limit:.1f} dB")
+    check_db(y, l_ref, limit, f"feedback in its own launch ({fb_spectra})")
+
+
+def test_fused_feedback_with_many_microphones_and_long_paths(rta):
+    """16 microphones x 8 loudspeakers, feedback paths longer than the synthesis
+    filters, non-uniform synthesis tiers: the fused loop against the oracle."""
+    B = 64
+    rng = np.random.default_rng(53)
+    hl = [[int(rng.integers(0, 3000)) for _ in range(8)] for _ in range(16)]
+    fl = [[int(rng.integers(0, 4000)) for _ in range(8)] for _ in range(16)]
+    h = make_filters(54, hl)
+    f = weak(make_filters(55, fl), 0.005)
+    m = workloads.white_noise(56, 16, 40 * B)
+    with rta.Convolver(h, B, scheme=[(64, 9), (512, 0)]) as cv:
+        cv.set_feedback(f)
+        y = cv.run(m)
+        cv.reset()
+        y2 = cv.run_device(m)
+    assert np.array_equal(y, y2)
+    l_ref, _, _ = oracle.feedback_loop(m, h, f, B)
+    check_db(y, l_ref, FP32_DB, "fused feedback 16 mics")
