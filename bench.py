@@ -305,7 +305,8 @@ def sweep_point(torch, rta, workloads, B, L, seconds, fs, spectra, fb_seconds=No
             "x_real_time": (B / fs) / (us * 1e-6), "deadline_us": deadline,
             "paced_p50_us": float(np.percentile(lat_us, 50)),
             "paced_p99_us": float(np.percentile(lat_us, 99)),
-            "paced_max_us": float(lat_us.max()), "xruns": int(np.sum(lat_us > deadline)),
+            "paced_max_us": float(lat_us.max()), "paced_max_at": int(np.argmax(lat_us)),
+            "paced_blocks": len(lat), "xruns": int(np.sum(lat_us > deadline)),
             "spectra_mb": info["spectra_bytes"] / 1e6}
 
 
