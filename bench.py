@@ -23,6 +23,7 @@ Printed on one JSON line:
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -41,6 +42,20 @@ METRIC = "real-time factor + p99 block latency, 32 out × 10 s filters, B=128 @4
 
 def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
+
+
+class no_gc:
+    """Python's cyclic garbage collector off inside a latency loop: a full
+    collection triggered by the binding's small allocations would otherwise
+    land inside a timed call (the library itself allocates nothing per
+    block)."""
+
+    def __enter__(self):
+        gc.collect()
+        gc.disable()
+
+    def __exit__(self, *exc):
+        gc.enable()
 
 
 def kernel_source_hash() -> str:
@@ -66,29 +81,41 @@ def measured_traffic(workload: str, spectra: str):
     return d.get("traffic_bytes_per_launch")
 
 
-def cpu_baseline(wl, filt, x, max_channels: int):
+def cpu_baseline(wl, filt, x, max_channels: int, y_gpu=None, reps: int = 3):
     """Time the oracle's FFT overlap-save over the first `max_channels`
-    outputs of the whole signal; scale to the full job."""
+    outputs of the whole signal (one warm-up, median of `reps` runs); scale to
+    the full job.  With y_gpu ([L][n] of the GPU's outputs for the same
+    signal) also report the GPU's error against that oracle result."""
     import oracle
     L = wl.n_out
     nch = min(L, max_channels)
     sub = [row[:nch] for row in filt]
     oracle.fftols(x[:, :wl.block * 8], [[f[:wl.block] for f in row] for row in sub], wl.block * 8)
-    t0 = time.perf_counter()
-    oracle.fftols(x, sub, x.shape[1])
-    dt = time.perf_counter() - t0
+    times = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        y_ref = oracle.fftols(x, sub, x.shape[1])
+        times.append(time.perf_counter() - t0)
+    dt = float(np.median(times))
     audio_s = x.shape[1] / wl.fs
     full_s = dt * L / nch
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {
+    res = {
         "value": audio_s / full_s,
         "unit": "x real-time (audio s / wall s)",
         "cores": min(threads, nch),
         "kind": "oracle",
         "sample": (f"FP64 single-partition FFT overlap-save over all {x.shape[1]} samples "
-                   f"({audio_s:.2f} s) of {nch} of {L} outputs in {dt:.2f} s, scaled to {L} "
-                   "outputs; offline (one FFT per filter), no per-block latency"),
+                   f"({audio_s:.2f} s) of {nch} of {L} outputs, median of {reps} runs of "
+                   f"{dt:.2f} s, scaled to {L} outputs; offline (one FFT per filter), no "
+                   "per-block latency"),
     }
+    if y_gpu is not None:
+        err = oracle.error_db(y_gpu[:nch, :x.shape[1]], y_ref)
+        res["gpu_error_db"] = {"max": float(err.max()), "mean": float(err.mean()),
+                               "outputs": nch, "samples": int(x.shape[1]),
+                               "vs": "relative RMS per output vs this oracle result"}
+    return res
 
 
 def read_probes(torch, rta, nbytes: int, grid: int, stream, reps: int = 20):
@@ -193,6 +220,8 @@ def serve_bench(args, torch, rta, workloads) -> dict:
     th = threading.Thread(target=control, daemon=True)
     th.start()
     lat, live, mbpb = [], [], []
+    gc.collect()
+    gc.disable()
     nxt = time.perf_counter()
     for n in range(n_blocks):
         nxt += period
@@ -211,6 +240,7 @@ def serve_bench(args, torch, rta, workloads) -> dict:
             time.sleep(rem - 2e-4)
         while time.perf_counter() < nxt:
             pass
+    gc.enable()
     state["done"] = True
     th.join()
     info, _ = srv.query()
@@ -285,17 +315,18 @@ def sweep_point(torch, rta, workloads, B, L, seconds, fs, spectra, fb_seconds=No
     lat = []
     period = B / fs
     paced = max(20, min(paced, int(2.0 / period)))  # at most about 2 s of audio
-    nxt = time.perf_counter()
-    for i in range(paced):
-        nxt += period
-        t = time.perf_counter()
-        rta.rta_process(cv.ctx, blocks[i % 64], out)
-        lat.append(time.perf_counter() - t)
-        rem = nxt - time.perf_counter()
-        if rem > 3e-4:
-            time.sleep(rem - 2e-4)
-        while time.perf_counter() < nxt:
-            pass
+    with no_gc():
+        nxt = time.perf_counter()
+        for i in range(paced):
+            nxt += period
+            t = time.perf_counter()
+            rta.rta_process(cv.ctx, blocks[i % 64], out)
+            lat.append(time.perf_counter() - t)
+            rem = nxt - time.perf_counter()
+            if rem > 3e-4:
+                time.sleep(rem - 2e-4)
+            while time.perf_counter() < nxt:
+                pass
     info = cv.info()
     cv.close()
     lat_us = np.array(lat) * 1e6
@@ -473,26 +504,28 @@ def main() -> int:
     for i in range(16):
         rta.rta_process(cv.ctx, np.ascontiguousarray(x[:, i * B:(i + 1) * B]), out)
     cv.reset()
-    for i in range(args.latency_blocks):
-        blk = np.ascontiguousarray(x[:, (i % nblk) * B:(i % nblk + 1) * B])
-        t = time.perf_counter()
-        rta.rta_process(cv.ctx, blk, out)
-        lat.append(time.perf_counter() - t)
+    with no_gc():
+        for i in range(args.latency_blocks):
+            blk = np.ascontiguousarray(x[:, (i % nblk) * B:(i % nblk + 1) * B])
+            t = time.perf_counter()
+            rta.rta_process(cv.ctx, blk, out)
+            lat.append(time.perf_counter() - t)
     lat_us = np.array(lat) * 1e6
     deadline = rta.deadline_us(B, fs)
     paced = None
     if args.paced_blocks:
         plat = []
         period = B / fs
-        nxt = time.perf_counter()
-        for i in range(args.paced_blocks):
-            nxt += period
-            blk = np.ascontiguousarray(x[:, (i % nblk) * B:(i % nblk + 1) * B])
-            t = time.perf_counter()
-            rta.rta_process(cv.ctx, blk, out)
-            plat.append(time.perf_counter() - t)
-            while time.perf_counter() < nxt:
-                pass
+        with no_gc():
+            nxt = time.perf_counter()
+            for i in range(args.paced_blocks):
+                nxt += period
+                blk = np.ascontiguousarray(x[:, (i % nblk) * B:(i % nblk + 1) * B])
+                t = time.perf_counter()
+                rta.rta_process(cv.ctx, blk, out)
+                plat.append(time.perf_counter() - t)
+                while time.perf_counter() < nxt:
+                    pass
         plat_us = np.array(plat) * 1e6
         paced = {"blocks": args.paced_blocks,
                  "mode": "rta_process paced every B/fs, host memory, PCIe included",
@@ -508,7 +541,9 @@ def main() -> int:
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the oracle on the host cores ...")
-        cpu = cpu_baseline(wl, filt, x[:, :wl.n_blocks * B], args.cpu_channels)
+        nb_cmp = min(wl.n_blocks, nblk)
+        y_gpu = yb[:nb_cmp].permute(1, 0, 2).reshape(L, nb_cmp * B).cpu().numpy()
+        cpu = cpu_baseline(wl, filt, x[:, :nb_cmp * B], args.cpu_channels, y_gpu)
 
     n_h = wl.max_len()
     lens = [int(np.asarray(f).size) for row in filt for f in row]

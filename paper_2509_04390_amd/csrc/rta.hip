@@ -445,6 +445,23 @@ int build_plan(rta_ctx* c, Plan& plan) {
     if (R <= 0) {
       const int64_t target_items = std::max(1, c->tail_items);
       R = (int)std::max<int64_t>(8, (total_rows * nslice + target_items - 1) / target_items);
+      // XCD balance: the partition ranges of one input form one bucket per
+      // range (all groups, all slices), spread over the 8 XCDs; make the
+      // number of ranges of the longest (group, input) times the inputs a
+      // multiple of 8 so every XCD gets as many (measured, 1 -> 32 x 10 s:
+      // 60 ranges 27.5 us, 64 ranges 24.4 us)
+      int kmax = 0;
+      for (const Group& gr : plan.groups)
+        for (int q = 0; q < c->Q; ++q) kmax = std::max(kmax, group_rows(T, gr, q) - 2);
+      if (fixed) kmax = std::max(0, T.kcap - 2);
+      int step = kXcds;
+      for (int qq = c->Q; qq % 2 == 0 && step > 1; qq /= 2) step /= 2;  // 8 / gcd(Q, 8)
+      if ((kmax + R - 1) / R >= kXcds)  // the largest R' <= R giving a multiple of step
+        for (int r2 = R; r2 >= 8; --r2)
+          if (((kmax + r2 - 1) / r2) % step == 0) {
+            R = r2;
+            break;
+          }
     }
     c->rows_per_item = R;
     const int nch_cap = (cap_rows + R - 1) / R;
