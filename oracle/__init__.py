@@ -14,7 +14,9 @@ for each (q,l) pair), in IEEE double, in two independent forms:
   successive input segments; only wrap-free samples kept, Sec. IV step 3),
   with the oracle's own radix-2 FFT (``fft``);
 * ``feedback_loop``: the auralization step with feedback cancellation
-  (Sec. III-A Eq. 3, Sec. V), block-recursive, direct sums.
+  (Sec. III-A Eq. 3, Sec. V), block-recursive, direct sums;
+* ``serve_loop``: the same loop when sources join and leave microphone slots
+  (each source with its own filter row, the feedback paths fixed per slot).
 
 The C code lives in ``rta_oracle.c`` and is built with gcc by
 ``build_library()``.  Inputs: ``x`` is ``[Q][n_x]`` (any float array; it is
@@ -66,8 +68,12 @@ def _load():
                                       dp, dp, dp]
     lib.orc_fftols.argtypes = [ctypes.c_int, ctypes.c_int, dp, i64, dp, ip,
                                i64, dp]
+    lib.orc_max_threads.argtypes = []
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    lib.orc_serve_loop.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, i64, i64,
+                                   i32p, ip, ip, dp, ip, dp, ip, dp, dp, dp]
     for f in (lib.orc_direct_range, lib.orc_direct_at, lib.orc_fft,
-              lib.orc_fftols, lib.orc_feedback_loop):
+              lib.orc_fftols, lib.orc_feedback_loop, lib.orc_max_threads, lib.orc_serve_loop):
         f.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -155,6 +161,47 @@ def feedback_loop(m, synth, feedback, block: int):
                                      _ip(foff), _dp(l_out), _dp(c_out), _dp(mt)),
            "feedback_loop")
     return l_out, c_out, mt
+
+
+def serve_loop(m, sources, feedback, block: int):
+    """Feedback-cancellation loop with sources that join and leave microphone
+    slots (a reading of Sec. III-A Eq. 1-3 and Sec. V; see rta_oracle.c).
+
+    m: [Q][N] microphone signals, one row per slot; sources: list of
+    (slot, first_block, end_block, filters) with `filters` a length-L list of
+    1-D arrays (None/empty = no path), live during blocks
+    [first_block, end_block); feedback: Q x L nested paths f_ql (loudspeaker
+    l to slot q) or None.  Returns (l [L][N], c [Q][N], mt [Q][N])."""
+    m = np.ascontiguousarray(np.atleast_2d(np.asarray(m, dtype=np.float64)))
+    Q, N = m.shape
+    if not sources:
+        raise ValueError("at least one source is needed")
+    L = len(sources[0][3])
+    rows = [list(src[3]) for src in sources]
+    _, h, hoff, S, L2 = _pack(np.zeros((len(rows), 1)), rows)
+    if L2 != L:
+        raise ValueError("every source needs L filters")
+    if feedback is None:
+        feedback = [[None] * L for _ in range(Q)]
+    _, f, foff, Q2, L3 = _pack(m, feedback)
+    if (Q2, L3) != (Q, L):
+        raise ValueError("feedback must be Q x L")
+    slot = np.ascontiguousarray([s[0] for s in sources], dtype=np.int32)
+    a = np.ascontiguousarray([s[1] for s in sources], dtype=np.int64)
+    b = np.ascontiguousarray([s[2] for s in sources], dtype=np.int64)
+    l_out = np.zeros((L, N))
+    c_out = np.zeros((Q, N))
+    mt = np.zeros((Q, N))
+    _check(_load().orc_serve_loop(Q, L, S, _dp(m), N, int(block),
+                                  slot.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                  _ip(a), _ip(b), _dp(h), _ip(hoff), _dp(f), _ip(foff),
+                                  _dp(l_out), _dp(c_out), _dp(mt)), "serve_loop")
+    return l_out, c_out, mt
+
+
+def max_threads() -> int:
+    """Threads the oracle's OpenMP loops use in this process."""
+    return int(_load().orc_max_threads())
 
 
 def fft(z, inverse: bool = False) -> np.ndarray:

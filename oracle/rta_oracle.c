@@ -38,6 +38,21 @@
  * i.e. the feedback estimate of one block is subtracted from the next block
  * of microphone samples.  Every sum is the direct form above.
  *
+ * Serving with feedback cancellation (the same loop with sources that come
+ * and go; a reading of Sec. III-A Eq. 1-3 and Sec. V for a system whose
+ * talkers change): Q microphone slots with fixed feedback paths f_ql, and
+ * sources s, each bound to one slot q_s, live during blocks [a_s, b_s)
+ * (one source per slot at a time) and carrying its own filter row h_sl.
+ * Per block n, for t in [nB, (n+1)B):
+ *     mt_q[t] = m_q[t] - c_q[t - B]   if a source of slot q is live in n,
+ *               0                      otherwise;
+ *     x_s[t]  = mt_{q_s}[t] if a_s <= n < b_s, else 0;
+ *     l_l[t]  = sum_s sum_j h_sl[j] x_s[t - j];
+ *     c_q[t]  = sum_l sum_j f_ql[j] l_l[t - j].
+ * A source that has left keeps ringing through its own filters (its input
+ * is zero from b_s on); with every slot live throughout and h_sl the row of
+ * slot q_s, this is the loop above.
+ *
  * Return codes: 0 on success, -1 on an invalid argument, -2 if memory for
  * the FFT work buffers cannot be allocated.
  */
@@ -45,10 +60,22 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #ifndef M_PI
 #define M_PI 3.14159265358979323846
 #endif
+
+/* Threads the OpenMP loops below run on (1 without OpenMP). */
+int orc_max_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 static int valid_layout(int Q, int L, const int64_t* off) {
     if (Q <= 0 || L <= 0 || off == NULL) return 0;
@@ -296,5 +323,67 @@ int orc_feedback_loop(int P, int L, const double* m, int64_t N, int64_t B,
             }
     }
     if (mt_out == NULL) free(mt);
+    return 0;
+}
+
+/* Serving loop with feedback cancellation (see the file header).  m is
+ * [Q][N]; source s has slot src_slot[s], live blocks [src_a[s], src_b[s])
+ * and filters h[hoff[s*L+l] .. hoff[s*L+l+1]) to output l; f is a Q x L
+ * pair array with offsets foff.  l_out is [L][N], c_out and mt_out [Q][N]. */
+int orc_serve_loop(int Q, int L, int S, const double* m, int64_t N, int64_t B,
+                   const int32_t* src_slot, const int64_t* src_a, const int64_t* src_b,
+                   const double* h, const int64_t* hoff, const double* f,
+                   const int64_t* foff, double* l_out, double* c_out, double* mt_out) {
+    if (Q <= 0 || L <= 0 || S < 0 || m == NULL || N < 0 || B < 1 || l_out == NULL ||
+        c_out == NULL || mt_out == NULL || !valid_layout(Q, L, foff))
+        return -1;
+    if (S > 0 && (src_slot == NULL || src_a == NULL || src_b == NULL || !valid_layout(S, L, hoff)))
+        return -1;
+    for (int s = 0; s < S; ++s)
+        if (src_slot[s] < 0 || src_slot[s] >= Q || src_b[s] < src_a[s]) return -1;
+    /* x_s: the input each source sees */
+    double* x = (double*)calloc((size_t)(S > 0 ? S : 1) * (size_t)(N > 0 ? N : 1), sizeof(double));
+    if (x == NULL) return -2;
+    for (int64_t t0 = 0; t0 < N; t0 += B) {
+        const int64_t n = t0 / B;
+        const int64_t t1 = t0 + B < N ? t0 + B : N;
+        for (int q = 0; q < Q; ++q) {
+            int live = 0;
+            for (int s = 0; s < S; ++s)
+                if (src_slot[s] == q && src_a[s] <= n && n < src_b[s]) live = 1;
+            for (int64_t t = t0; t < t1; ++t)
+                mt_out[(int64_t)q * N + t] =
+                    live ? m[(int64_t)q * N + t] - (t >= B ? c_out[(int64_t)q * N + t - B] : 0.0)
+                         : 0.0;
+        }
+        for (int s = 0; s < S; ++s) {
+            const int on = src_a[s] <= n && n < src_b[s];
+            for (int64_t t = t0; t < t1; ++t)
+                x[(int64_t)s * N + t] = on ? mt_out[(int64_t)src_slot[s] * N + t] : 0.0;
+        }
+#pragma omp parallel for schedule(static)
+        for (int l = 0; l < L; ++l)
+            for (int64_t t = t0; t < t1; ++t) {
+                double acc = 0.0;
+                for (int s = 0; s < S; ++s) {
+                    int64_t pi = (int64_t)s * L + l;
+                    acc += pair_sample(x + (int64_t)s * N, t1, h + hoff[pi],
+                                       hoff[pi + 1] - hoff[pi], t);
+                }
+                l_out[(int64_t)l * N + t] = acc;
+            }
+#pragma omp parallel for schedule(static)
+        for (int q = 0; q < Q; ++q)
+            for (int64_t t = t0; t < t1; ++t) {
+                double acc = 0.0;
+                for (int l = 0; l < L; ++l) {
+                    int64_t pi = (int64_t)q * L + l;
+                    acc += pair_sample(l_out + (int64_t)l * N, t1, f + foff[pi],
+                                       foff[pi + 1] - foff[pi], t);
+                }
+                c_out[(int64_t)q * N + t] = acc;
+            }
+    }
+    free(x);
     return 0;
 }

@@ -300,3 +300,82 @@ def test_feedback_loop_is_linear_and_block_causal():
     l3 = oracle.feedback_loop(m3, h, f, B)[0]
     assert np.array_equal(l3[:, :5 * B], l1[:, :5 * B])
     assert not np.allclose(l3[:, 5 * B:], l1[:, 5 * B:])
+
+
+# ----------------------------------------------------------------------------
+# Serving loop: the feedback loop when sources join and leave microphone
+# slots (reading of Sec. III-A Eq. 1-3 and Sec. V for changing talkers)
+# ----------------------------------------------------------------------------
+
+def test_serve_loop_with_every_slot_always_live_is_the_feedback_loop():
+    # one source per slot, live throughout, carrying that slot's filter row:
+    # the plain loop (itself pinned above)
+    r = rng(40)
+    P, L, N, B = 3, 2, 480, 16
+    h = _rand_filters(r, P, L, 60)
+    f = _rand_filters(r, P, L, 25, scale=0.01)
+    m = r.standard_normal((P, N))
+    srcs = [(p, 0, N // B, h[p]) for p in range(P)]
+    got = oracle.serve_loop(m, srcs, f, B)
+    want = oracle.feedback_loop(m, h, f, B)
+    for g, w in zip(got, want):
+        assert np.max(np.abs(g - w)) < 1e-12
+
+
+def test_serve_loop_without_feedback_is_each_source_over_its_live_blocks():
+    # no feedback paths: each source's filters applied to its slot's signal
+    # cut to its live blocks (numpy.convolve), summed; a source that left
+    # keeps ringing through its own filters
+    r = rng(41)
+    Q, L, N, B = 2, 3, 640, 16
+    m = r.standard_normal((Q, N))
+    srcs = [(0, 2, 15, [r.standard_normal(70) for _ in range(L)]),
+            (1, 0, 40, [r.standard_normal(33), None, r.standard_normal(90)]),
+            (0, 22, 31, [None, r.standard_normal(120), r.standard_normal(5)])]
+    l, c, mt = oracle.serve_loop(m, srcs, None, B)
+    assert np.all(c == 0.0)
+    want = np.zeros((L, N))
+    for q, a, b, row in srcs:
+        x = np.zeros(N)
+        x[a * B:b * B] = m[q, a * B:b * B]
+        for j in range(L):
+            if row[j] is not None:
+                want[j] += np.convolve(x, row[j])[:N]
+    assert np.max(np.abs(l - want)) < 1e-11
+    # slot 0 is dead in blocks [15, 22) and [31, 40): its input reads as zero
+    assert np.all(mt[0, 15 * B:22 * B] == 0.0) and np.all(mt[0, 31 * B:] == 0.0)
+    assert np.array_equal(mt[1], m[1])
+
+
+def test_serve_loop_gain_feedback_comb_stops_with_the_source():
+    # H = delta, F-hat = a delta, one source live in blocks [3, 7): an impulse
+    # at its first sample gives mt[(3 + k) B] = (-a)^k while it is live, then
+    # silence; the loudspeaker carries mt (delta filter)
+    B, a, N = 4, 0.5, 48
+    m = np.zeros((1, N))
+    m[0, 3 * B] = 1.0
+    m[0, 9 * B] = 7.0           # after the source left: ignored
+    l, c, mt = oracle.serve_loop(m, [(0, 3, 7, [np.array([1.0])])], [[np.array([a])]], B)
+    want = np.zeros(N)
+    for k in range(4):
+        want[(3 + k) * B] = (-a) ** k
+    assert np.array_equal(mt[0], want)
+    assert np.array_equal(l[0], want)
+    assert np.array_equal(c[0], a * want)
+
+
+def test_serve_loop_ignores_a_slot_signal_while_no_source_is_live():
+    r = rng(42)
+    Q, L, N, B = 2, 2, 320, 16
+    m = r.standard_normal((Q, N))
+    f = _rand_filters(r, Q, L, 20, scale=0.02)
+    srcs = [(0, 0, 6, [r.standard_normal(40) for _ in range(L)]),
+            (1, 4, 20, [r.standard_normal(30) for _ in range(L)]),
+            (0, 12, 20, [r.standard_normal(25) for _ in range(L)])]
+    base = oracle.serve_loop(m, srcs, f, B)
+    m2 = m.copy()
+    m2[0, 6 * B:12 * B] = 1e6 * r.standard_normal(6 * B)   # slot 0 dead there
+    m2[1, :4 * B] = -3.0                                     # slot 1 dead there
+    other = oracle.serve_loop(m2, srcs, f, B)
+    for g, w in zip(other, base):
+        assert np.array_equal(g, w)
