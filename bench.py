@@ -18,7 +18,8 @@ Printed on one JSON line:
                 input and output blocks) / its mean duration from HIP events
                 on the launch stream, vs 8 TB/s;
   cpu_baseline  the FP64 oracle (single-partition FFT overlap-save) timed on
-                the host cores over a bounded sample of the same workload.
+                the host cores over the workload's whole signal (independent
+                of --steps), with the GPU output's error against it.
 """
 from __future__ import annotations
 
@@ -81,40 +82,65 @@ def measured_traffic(workload: str, spectra: str):
     return d.get("traffic_bytes_per_launch")
 
 
+def host_cpu() -> dict:
+    """The host's CPU model and the cores this process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count() or 1
+    return {"model": model, "nproc": nproc, "cpu_count": os.cpu_count()}
+
+
 def cpu_baseline(wl, filt, x, max_channels: int, y_gpu=None, reps: int = 3):
     """Time the oracle's FFT overlap-save over the first `max_channels`
-    outputs of the whole signal (one warm-up, median of `reps` runs); scale to
-    the full job.  With y_gpu ([L][n] of the GPU's outputs for the same
-    signal) also report the GPU's error against that oracle result."""
+    outputs of the whole signal `x` (one warm-up, median of `reps` runs, one
+    run only if a run takes more than 10 s); scale to the full job.  With
+    y_gpu ([L][n] of the GPU's outputs for the same signal) also report the
+    GPU's error against that oracle result."""
     import oracle
     L = wl.n_out
     nch = min(L, max_channels)
     sub = [row[:nch] for row in filt]
+    threads = oracle.max_threads()
     oracle.fftols(x[:, :wl.block * 8], [[f[:wl.block] for f in row] for row in sub], wl.block * 8)
     times = []
     for _ in range(reps):
         t0 = time.perf_counter()
         y_ref = oracle.fftols(x, sub, x.shape[1])
         times.append(time.perf_counter() - t0)
+        if times[-1] > 10.0:
+            break
     dt = float(np.median(times))
     audio_s = x.shape[1] / wl.fs
     full_s = dt * L / nch
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cpu = host_cpu()
     res = {
         "value": audio_s / full_s,
         "unit": "x real-time (audio s / wall s)",
         "cores": min(threads, nch),
         "kind": "oracle",
-        "sample": (f"FP64 single-partition FFT overlap-save over all {x.shape[1]} samples "
-                   f"({audio_s:.2f} s) of {nch} of {L} outputs, median of {reps} runs of "
-                   f"{dt:.2f} s, scaled to {L} outputs; offline (one FFT per filter), no "
-                   "per-block latency"),
+        "sample": (f"FP64 single-partition FFT overlap-save (the oracle as committed) over the "
+                   f"workload's whole signal, {x.shape[1]} samples ({audio_s:.2f} s), for "
+                   f"{nch} of {L} outputs on {min(threads, nch)} OpenMP threads (one per "
+                   f"output at most); median of {len(times)} runs of {dt:.2f} s, scaled to "
+                   f"{L} outputs; offline (one FFT per filter), no per-block latency"),
+        "host": {**cpu, "omp_threads": threads},
     }
     if y_gpu is not None:
         err = oracle.error_db(y_gpu[:nch, :x.shape[1]], y_ref)
         res["gpu_error_db"] = {"max": float(err.max()), "mean": float(err.mean()),
                                "outputs": nch, "samples": int(x.shape[1]),
-                               "vs": "relative RMS per output vs this oracle result"}
+                               "vs": "relative RMS per output vs this oracle result, "
+                                     "GPU output of the same whole signal"}
     return res
 
 
@@ -368,7 +394,7 @@ def sweeps(args, torch, rta, workloads) -> dict:
             "defaults": "1 input -> 32 outputs, 10 s filters, B = 128"}
 
 
-def main() -> int:
+def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
@@ -402,7 +428,7 @@ def main() -> int:
     ap.add_argument("--serve-life", type=float, default=2.0, help="mean source lifetime, s")
     ap.add_argument("--serve-budget-frac", type=float, default=0.5,
                     help="admission budget: this fraction of deadline x probed bandwidth")
-    args = ap.parse_args()
+    args = ap.parse_args(argv)
 
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -477,7 +503,9 @@ def main() -> int:
     pout = [yb[i].data_ptr() for i in range(nblk)]
     sh = stream.cuda_stream
     launch = rta._lib.rta_process_device
-    rta.rta_timing_enable(cv.ctx, args.timing_every)
+    # spans must fit inside the timed steps, or none would complete
+    every = max(1, min(args.timing_every, args.steps))
+    rta.rta_timing_enable(cv.ctx, every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -488,12 +516,19 @@ def main() -> int:
     wall = time.perf_counter() - t0
     n_timed, kern_ms = rta.rta_timing_read(cv.ctx)
     rta.rta_timing_enable(cv.ctx, False)
-    kern_us = 1e3 * kern_ms / max(1, n_timed)
     ms_per_step = 1e3 * wall / args.steps
+    if n_timed > 0:
+        kern_us = 1e3 * kern_ms / n_timed
+        timing_how = (f"HIP events on the launch stream around spans of {every} back-to-back "
+                      f"blocks inside the timed region ({n_timed} blocks): per-block time "
+                      "including the gaps between launches, an upper bound on the kernel's")
+    else:  # no complete span (cannot happen with every <= steps; kept as a guard)
+        kern_us = 1e3 * ms_per_step
+        timing_how = "wall clock per step (no event span completed): an upper bound"
     audio_per_step = B / fs
     value = audio_per_step / (ms_per_step / 1e3)
     log(f"timed {args.steps} steps: {ms_per_step * 1e3:.1f} us/step; {kern_us:.1f} us per block "
-        f"in event-timed spans of {args.timing_every} ({n_timed} blocks)")
+        f"in event-timed spans of {every} ({n_timed} blocks)")
     probes = read_probes(torch, rta, int(info["spectra_bytes"]), info["grid"], stream)
 
     # synchronous host-memory blocks: per-block latency including PCIe (after
@@ -540,10 +575,24 @@ def main() -> int:
     traffic = measured_traffic(wl.name, args.spectra)
     cpu = None
     if not args.no_cpu_baseline:
-        log("timing the oracle on the host cores ...")
-        nb_cmp = min(wl.n_blocks, nblk)
-        y_gpu = yb[:nb_cmp].permute(1, 0, 2).reshape(L, nb_cmp * B).cpu().numpy()
-        cpu = cpu_baseline(wl, filt, x[:, :nb_cmp * B], args.cpu_channels, y_gpu)
+        # the workload's whole signal, whatever --steps is: the GPU streams it
+        # once more from a reset context, the oracle processes it in one go
+        x_full = wl.signal_array()
+        nb_full = x_full.shape[1] // B
+        cv.reset()
+        xf = torch.from_numpy(x_full[:, :nb_full * B].reshape(Q, nb_full, B)
+                              .transpose(1, 0, 2).copy()).cuda()
+        yf = torch.empty((nb_full, L, B), dtype=torch.float32, device="cuda")
+        for i in range(nb_full):
+            cv.process_device(xf[i], yf[i], stream)
+        torch.cuda.synchronize()
+        y_gpu = yf.permute(1, 0, 2).reshape(L, nb_full * B).cpu().numpy()
+        del xf, yf
+        log(f"timing the oracle on the host cores over {nb_full} blocks ...")
+        cpu = cpu_baseline(wl, filt, x_full[:, :nb_full * B], args.cpu_channels, y_gpu)
+        log(f"cpu baseline: {cpu['value']:.2f} x real time on {cpu['cores']} threads "
+            f"({cpu['host']['model']}, nproc {cpu['host']['nproc']}); GPU error "
+            f"{cpu['gpu_error_db']['max']:.1f} dB max")
 
     n_h = wl.max_len()
     lens = [int(np.asarray(f).size) for row in filt for f in row]
@@ -593,10 +642,7 @@ def main() -> int:
             "traffic": traffic,
             "bytes_per_launch": bytes_per_launch,
             "kernel_us_mean": kern_us,
-            "kernel_us_timing": (f"HIP events on the launch stream around spans of "
-                                 f"{args.timing_every} back-to-back blocks inside the timed "
-                                 f"region ({n_timed} blocks): per-block time including the "
-                                 "gaps between launches, an upper bound on the kernel's"),
+            "kernel_us_timing": timing_how,
         },
         "read_probe": probes,
         "autotune": tuned,

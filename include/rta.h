@@ -109,6 +109,8 @@ typedef struct rta_info {
                                      load in the multiply-accumulate       */
     int32_t rows_per_item;        /* partitions per workgroup work item    */
     int32_t poisoned;             /* 1 after RTA_E_DEVICE                  */
+    int32_t feedback_paths;       /* 1 while rta_set_feedback paths are set */
+    int32_t feedback_fused;       /* 1 if they run inside the block launch  */
 } rta_info;
 
 /* Create a context.
@@ -213,13 +215,48 @@ int rta_process_device(rta_ctx* ctx, const float* d_in, float* d_out,
  * From then on block n's input is m_n - c_{n-1}: the feedback estimate
  * c = F * y, computed from the context's own output y by a second,
  * uniformly partitioned convolution (partition = block) on the GPU, is
- * subtracted from the next block of microphone samples.  That convolution is
- * launched on the same stream after each block's output is complete, so it
- * is not on rta_process's latency path.  fb == NULL removes the feedback
- * paths.  Resets the context (as rta_reset).  Taps are copied during the
- * call. */
+ * subtracted from the next block of microphone samples.
+ *
+ * Where it runs, and what it costs on the latency path:
+ *   - Fused (rta_info.feedback_fused = 1): when `spectra` equals the
+ *     context's spectra type and the combined launch fits in LDS, the
+ *     feedback convolution runs inside each block's single launch.  Its
+ *     output workgroups (one per microphone, dispatched first) compute
+ *     c_{n-1}; the synthesis output workgroups of block n reduce their own
+ *     partial sums meanwhile, then WAIT for c_{n-1} before packing their
+ *     input, and after emitting y(n) they transform it into the feedback
+ *     delay line.  That wait is on rta_process's latency path: it adds the
+ *     feedback heads' reduction, their partitions 0 and 1 over every output
+ *     and one inverse FFT (measured 14-24 us per block for 1 -> 32 outputs
+ *     and 0.1-5 s paths).  The wait is bounded: if it gives up, the block
+ *     fails with RTA_E_DEVICE (from rta_process, or from the next
+ *     rta_process_device / rta_query / rta_reset call) and the context is
+ *     poisoned.
+ *   - Separate: with another spectra type, the feedback convolution is a
+ *     second launch on the same stream after each block.  It is off the
+ *     latency path of the block that launches it, but the next block's
+ *     launch is stream-ordered after it.
+ *
+ * Serving contexts (rta_serve_create): input slot q is microphone q and
+ * f_ql its path from loudspeaker l.  The paths belong to the slot, not to
+ * the source admitted into it, and stay in place across admissions and
+ * releases.  While a slot is live its input is m_q - c_q (previous block);
+ * while it is not live its input reads as zero, whatever m_q and c_q are
+ * (its estimate is still computed, and unused).
+ *
+ * fb == NULL removes the paths.  Resets the context (as rta_reset; a serving
+ * context keeps its live sources and frees released ones).  Taps are copied
+ * during the call. */
 int rta_set_feedback(rta_ctx* ctx, const float* const* fb, const int64_t* lengths,
                      int32_t spectra);
+
+/* Test aid for the failure path of the fused feedback wait (above): bound
+ * the synthesis workgroups' wait to max_polls polls (>= 1; default 2^24),
+ * and with never_ready = 1 make the awaited count unreachable, so that every
+ * fused block gives up after max_polls polls, reports RTA_E_DEVICE and
+ * poisons the context.  Every kernel still runs to completion.  No device
+ * call; RTA_E_ARG for max_polls < 1 or never_ready not in {0, 1}. */
+int rta_test_feedback_wait(rta_ctx* ctx, int32_t max_polls, int32_t never_ready);
 
 /* Zero all delay lines, input history, output rings and the block index, as
  * if the context had just been created.  Synchronous. */
@@ -230,18 +267,20 @@ int rta_query(rta_ctx* ctx, rta_info* info);
 
 /* Block timing (profiling aid).  Each block is one kernel launch (the heads
  * of this block and the multiply-accumulate of partitions >= 2 for the next
- * one; with later tiers or feedback paths, a second and third launch).
- * After rta_timing_enable(ctx, every) with every >= 1, the blocks launched by
- * rta_process() or rta_process_device() are timed in spans of `every`
- * consecutive blocks, each starting at a block index that is a multiple of
- * `every`: one HIP event on the launch stream before the span's first launch
- * and one after its last.  With every = 1 that brackets each block's kernels;
- * a longer span also counts the gaps between back-to-back launches but keeps
- * the event packets, which delay the stream, off most blocks.
- * rta_timing_read() waits for the recorded events and returns the number of
- * blocks in complete spans and their summed time in milliseconds, then
- * forgets them.  At most 65536 spans are kept.  rta_timing_enable(ctx, 0)
- * stops recording (a span still open is dropped); every < 0 is RTA_E_ARG. */
+ * one; with later tiers or an unfused feedback convolution, a second and
+ * third launch).  After rta_timing_enable(ctx, every) with every >= 1, the
+ * blocks launched by rta_process() or rta_process_device() are timed in spans
+ * of `every` consecutive blocks, the first span starting at the first block
+ * launched after the call: one HIP event on the launch stream before a span's
+ * first launch and one after its last.  With every = 1 that brackets each
+ * block's kernels; a longer span also counts the gaps between back-to-back
+ * launches but keeps the event packets, which delay the stream, off most
+ * blocks.  rta_timing_read() waits for the recorded events and returns the
+ * number of blocks in complete spans (0 if no span has completed) and their
+ * summed time in milliseconds, then forgets them; a span still open is
+ * dropped.  At most 65536 spans are kept.  rta_timing_enable(ctx, 0) stops
+ * recording (a span still open is dropped); rta_reset drops an open span and
+ * restarts the span grid at block 0; every < 0 is RTA_E_ARG. */
 int rta_timing_enable(rta_ctx* ctx, int32_t every);
 int rta_timing_read(rta_ctx* ctx, int64_t* blocks, double* block_ms);
 
@@ -289,9 +328,8 @@ int rta_probe_read(const void* d_buf, int64_t bytes, int32_t grid, float* d_sink
  * Threads: one thread may run rta_process / rta_process_device while one
  * other thread calls rta_serve_admit / rta_serve_release / rta_serve_query;
  * the block thread only takes a short lock at each block boundary.
- * rta_set_feedback and rta_autotune are not available for serving contexts
- * (RTA_E_UNSUPPORTED); rta_reset zeroes all state, keeps live sources and
- * frees released ones.
+ * rta_set_feedback attaches per-slot feedback paths (see above); rta_reset
+ * zeroes all state, keeps live sources and frees released ones.
  * ------------------------------------------------------------------------ */
 typedef struct rta_serve_config {
     int32_t n_slots;       /* source slots (inputs), >= 1                   */

@@ -100,6 +100,9 @@ struct FcArgs {
   int32_t tail0;             // tail index of its first item in the launch
   int32_t n_heads, head_slots;  // one head per feedback output; part of the grid
   int32_t Qf, Lf;            // its inputs (= synthesis outputs), outputs
+  int32_t wait_polls;        // bound of the synthesis heads' wait for c
+  uint32_t wait_bias;        // added to the wait's target (nonzero only to
+                             // test the give-up path: never reached)
 };
 
 struct KArgs {
@@ -134,6 +137,8 @@ struct KArgs {
                              // (null: every input is live)
   int32_t fc_on;             // the feedback convolution runs in this launch
   int32_t pad3;
+  int32_t* status;           // host-visible error word: a wait that gave up
+                             // stores 1 (system scope); checked by the host
   FcArgs fc;
 };
 
@@ -583,15 +588,20 @@ __device__ void head_work(const KArgs& A, const Group& grp, int gsel, float2* ld
 
   // fused feedback: wait until every feedback head of this launch has
   // published c_{n-1} (they are dispatched first and wait for nothing; the
-  // spin is bounded all the same)
+  // spin is bounded all the same, and a wait that gives up is reported
+  // through the status word, which fails the block on the host)
   if (A.fc_on) {
     if (tid == 0) {
-      const unsigned int target = (unsigned int)((n + 1) * A.fc.n_heads);
-      for (int it = 0; it < (1 << 24); ++it) {
-        if ((int)(__hip_atomic_load(A.fc.done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) - target) >= 0)
+      const unsigned int target = (unsigned int)((n + 1) * A.fc.n_heads) + A.fc.wait_bias;
+      bool ready = false;
+      for (int it = 0; it < A.fc.wait_polls; ++it) {
+        if ((int)(__hip_atomic_load(A.fc.done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) - target) >= 0) {
+          ready = true;
           break;
+        }
         __builtin_amdgcn_s_sleep(2);
       }
+      if (!ready) __hip_atomic_store(A.status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
     __syncthreads();
   }

@@ -101,15 +101,19 @@ struct rta_ctx {
   float* h_in = nullptr;       // pinned host staging, mapped into the device
   float* h_out = nullptr;
   int64_t* h_flag = nullptr;
-  float* m_in = nullptr;       // device addresses of the three
+  int32_t* h_status = nullptr; // pinned error word the kernels may set
+  float* m_in = nullptr;       // device addresses of the four
   float* m_out = nullptr;
   int64_t* m_flag = nullptr;
+  int32_t* m_status = nullptr;
 
   rta_ctx* fc = nullptr;        // feedback convolution: outputs -> inputs
   float* d_y = nullptr;         // [L][B] copy of the output block (its input)
   float* d_c = nullptr;         // [Q][B] its output, subtracted next block
   bool fc_fused = false;        // it runs inside this context's launch
   unsigned int* fc_done = nullptr;  // its heads done (fused; monotonic)
+  int fc_wait_polls = 1 << 24;  // bound of the synthesis heads' wait for it
+  uint32_t fc_wait_bias = 0;    // nonzero only to test the give-up path
   int min_ring = 1;             // first tier's delay line has at least this many slots
 
   std::vector<int32_t> block_count_host;  // k_block items per phase (active list)
@@ -119,6 +123,7 @@ struct rta_ctx {
 
   bool poisoned = false;
   int timing = 0;                  // timed spans of this many blocks (0: off)
+  int64_t timing_base = 0;         // block index at rta_timing_enable
   bool span_open = false;          // a span's first event is recorded
   int timing_span_read = 1;        // blocks per recorded span
   std::vector<hipEvent_t> events;  // 2 per timed block
@@ -184,6 +189,16 @@ namespace {
       return RTA_E_DEVICE;                                   \
     }                                                        \
   } while (0)
+
+// A kernel that could not complete its work correctly (a bounded wait that
+// gave up) has set the context's error word: poison the context.
+int device_status(rta_ctx* c) {
+  if (c->h_status != nullptr && __atomic_load_n(c->h_status, __ATOMIC_ACQUIRE) != 0) {
+    c->poisoned = true;
+    return RTA_E_DEVICE;
+  }
+  return RTA_OK;
+}
 
 template <typename T>
 int dev_alloc(rta_ctx* c, T** p, size_t count) {
@@ -754,6 +769,7 @@ KArgs make_args(const rta_ctx* c, const float* in, float* out, int64_t n) {
   a.max_tier_items = c->max_tier_items;
   a.n_groups_total = c->n_groups;
   a.live = c->live;
+  a.status = c->m_status;
   if (c->fc != nullptr && c->fc_fused) {
     const rta_ctx* f = c->fc;
     const TierHost& T = f->tier[0];
@@ -784,6 +800,8 @@ KArgs make_args(const rta_ctx* c, const float* in, float* out, int64_t n) {
     F.head_slots = (f->L + kXcds - 1) / kXcds * kXcds;
     F.Qf = f->Q;
     F.Lf = f->L;
+    F.wait_polls = c->fc_wait_polls;
+    F.wait_bias = c->fc_wait_bias;
     a.fc_on = 1;
     a.sub = c->d_c;
   }
@@ -878,13 +896,13 @@ int launch_block(rta_ctx* c, const float* in, float* out, hipStream_t s, bool fl
   }
   const int phase = (int)(c->block % c->n_phase);
   const int n_tier = c->tier_count_host.empty() ? 0 : c->tier_count_host[phase];
-  // timing: a span of `timing` consecutive blocks starts at every block
-  // index that is a multiple of it; an event before its first launch and one
-  // after its last
+  // timing: spans of `timing` consecutive blocks, the first starting at the
+  // first block launched after rta_timing_enable; an event before a span's
+  // first launch and one after its last
   const int64_t every = c->timing;
-  const bool span_start = every > 0 && c->block % every == 0 &&
-                          c->events_used + 2 <= 2 * kMaxTimedBlocks;
-  const bool span_end = every > 0 && c->span_open && (c->block + 1) % every == 0;
+  const int64_t rel = c->block - c->timing_base;
+  const bool span_start = every > 0 && rel % every == 0 && c->events_used + 2 <= 2 * kMaxTimedBlocks;
+  const bool span_end = every > 0 && c->span_open && (rel + 1) % every == 0;
   if (span_start) {
     while (c->events.size() < c->events_used + 2) {
       hipEvent_t ev;
@@ -944,6 +962,8 @@ int zero_state(rta_ctx* c) {
   }
   __atomic_store_n(c->h_flag, (int64_t)0, __ATOMIC_RELEASE);
   c->block = 0;
+  c->timing_base = 0;  // a span still open is dropped
+  c->span_open = false;
   return RTA_OK;
 }
 
@@ -1309,13 +1329,17 @@ int create_impl(rta_ctx* c, const std::vector<int>& size, const std::vector<int>
       hipHostMalloc(reinterpret_cast<void**>(&c->h_out), sizeof(float) * (size_t)c->L * c->B,
                     hipHostMallocMapped) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&c->h_flag), sizeof(int64_t),
+                    hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&c->h_status), sizeof(int32_t),
                     hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
     (void)hipGetLastError();
     return RTA_E_NOMEM;
   }
+  __atomic_store_n(c->h_status, 0, __ATOMIC_RELEASE);
   HIP_TRY(c, hipHostGetDevicePointer(reinterpret_cast<void**>(&c->m_in), c->h_in, 0));
   HIP_TRY(c, hipHostGetDevicePointer(reinterpret_cast<void**>(&c->m_out), c->h_out, 0));
   HIP_TRY(c, hipHostGetDevicePointer(reinterpret_cast<void**>(&c->m_flag), c->h_flag, 0));
+  HIP_TRY(c, hipHostGetDevicePointer(reinterpret_cast<void**>(&c->m_status), c->h_status, 0));
 
   // LDS: the larger of a head's layout (HeadLds) and a tail item's row-group
   // reduction.  head_nq: as many inputs per pass as fit in 48 KB, at least 1.
@@ -1365,6 +1389,7 @@ void free_all(rta_ctx* c) {
   if (c->h_in) (void)hipHostFree(c->h_in);
   if (c->h_out) (void)hipHostFree(c->h_out);
   if (c->h_flag) (void)hipHostFree(c->h_flag);
+  if (c->h_status) (void)hipHostFree(c->h_status);
   if (c->stream) (void)hipStreamDestroy(c->stream);
 }
 
@@ -1794,6 +1819,7 @@ int rta_process(rta_ctx* c, const float* in, float* out) {
       next_check = clk::now() + std::chrono::milliseconds(1);
     }
   }
+  if ((st = device_status(c)) != RTA_OK) return st;
   std::memcpy(out, c->h_out, sizeof(float) * (size_t)c->L * c->B);
   return RTA_OK;
 }
@@ -1801,6 +1827,8 @@ int rta_process(rta_ctx* c, const float* in, float* out) {
 int rta_process_device(rta_ctx* c, const float* d_in, float* d_out, void* stream) {
   if (c == nullptr || d_in == nullptr || d_out == nullptr) return RTA_E_ARG;
   if (c->poisoned) return RTA_E_DEVICE;
+  const int st = device_status(c);  // set by a block launched earlier
+  if (st != RTA_OK) return st;
   return launch_block(c, d_in, d_out, static_cast<hipStream_t>(stream));
 }
 
@@ -1808,12 +1836,15 @@ int rta_reset(rta_ctx* c) {
   if (c == nullptr) return RTA_E_ARG;
   if (c->poisoned) return RTA_E_DEVICE;
   HIP_TRY(c, hipDeviceSynchronize());
+  const int st = device_status(c);
+  if (st != RTA_OK) return st;
   if (c->serve != nullptr) return serve_reset(c);
   return zero_state(c);
 }
 
 int rta_query(rta_ctx* c, rta_info* info) {
   if (c == nullptr || info == nullptr) return RTA_E_ARG;
+  (void)device_status(c);
   std::memset(info, 0, sizeof(*info));
   info->fs = c->fs;
   info->deadline_us = 1e6 * c->B / c->fs;
@@ -1840,35 +1871,41 @@ int rta_query(rta_ctx* c, rta_info* info) {
   info->outputs_per_group = c->G;
   info->rows_per_item = c->rows_per_item;
   info->poisoned = c->poisoned ? 1 : 0;
+  info->feedback_paths = c->fc != nullptr ? 1 : 0;
+  info->feedback_fused = c->fc != nullptr && c->fc_fused ? 1 : 0;
   return c->poisoned ? RTA_E_DEVICE : RTA_OK;
 }
 
 int rta_set_feedback(rta_ctx* c, const float* const* fb, const int64_t* lengths, int32_t spectra) {
   if (c == nullptr) return RTA_E_ARG;
   if (c->poisoned) return RTA_E_DEVICE;
-  if (c->serve != nullptr) return RTA_E_UNSUPPORTED;
+  // the feedback convolution runs outputs -> inputs: its filter [l][q] is
+  // f_ql; validated like rta_create's arguments (uniform partitions, P = B)
+  // before anything is touched
+  const int64_t np = (int64_t)c->Q * c->L;
+  std::vector<const float*> ft;
+  std::vector<int64_t> lt;
+  std::vector<int> size, count;
+  if (fb != nullptr) {
+    if (lengths == nullptr) return RTA_E_ARG;
+    ft.resize(np);
+    lt.resize(np);
+    for (int q = 0; q < c->Q; ++q)
+      for (int l = 0; l < c->L; ++l) {
+        ft[(int64_t)l * c->Q + q] = fb[(int64_t)q * c->L + l];
+        lt[(int64_t)l * c->Q + q] = lengths[(int64_t)q * c->L + l];
+      }
+    const int st = validate(c->fs, c->B, nullptr, c->L, c->Q, ft.data(), lt.data(), spectra, 0, size, count);
+    if (st != RTA_OK) return st;
+  }
   HIP_TRY(c, hipDeviceSynchronize());
   if (c->fc) {
     free_all(c->fc);
     delete c->fc;
     c->fc = nullptr;
   }
+  c->fc_fused = false;
   if (fb != nullptr) {
-    if (lengths == nullptr) return RTA_E_ARG;
-    // the feedback convolution runs outputs -> inputs: its filter [l][q]
-    // is f_ql
-    const int64_t np = (int64_t)c->Q * c->L;
-    std::vector<const float*> ft(np);
-    std::vector<int64_t> lt(np);
-    for (int q = 0; q < c->Q; ++q)
-      for (int l = 0; l < c->L; ++l) {
-        ft[(int64_t)l * c->Q + q] = fb[(int64_t)q * c->L + l];
-        lt[(int64_t)l * c->Q + q] = lengths[(int64_t)q * c->L + l];
-      }
-    // validated like rta_create's arguments (uniform partitions, P = B)
-    std::vector<int> size, count;
-    int st = validate(c->fs, c->B, nullptr, c->L, c->Q, ft.data(), lt.data(), spectra, 0, size, count);
-    if (st != RTA_OK) return st;
     // same outputs per group as this context, so its items can run in this
     // context's launch; at least 3 delay-line slots (this launch writes slot
     // n while its heads read n-1 and n-2)
@@ -1880,15 +1917,14 @@ int rta_set_feedback(rta_ctx* c, const float* const* fb, const int64_t* lengths,
     tu.tail_items = 512;
     tu.bin_slices = 8;
     rta_ctx* fc = nullptr;
-    st = create_ctx(&fc, c->fs, c->B, size, count, c->L, c->Q, ft.data(), lt.data(), spectra, 0, &tu,
-                    nullptr, 3);
+    int st = create_ctx(&fc, c->fs, c->B, size, count, c->L, c->Q, ft.data(), lt.data(), spectra, 0, &tu,
+                        nullptr, 3);
     if (st != RTA_OK) return st;
     c->fc = fc;
     if (c->d_y == nullptr) {
-      int s2;
-      if ((s2 = dev_alloc(c, &c->d_y, (size_t)c->L * c->B)) != RTA_OK) return s2;
-      if ((s2 = dev_alloc(c, &c->d_c, (size_t)c->Q * c->B)) != RTA_OK) return s2;
-      if ((s2 = dev_alloc(c, &c->fc_done, 1)) != RTA_OK) return s2;
+      if ((st = dev_alloc(c, &c->d_y, (size_t)c->L * c->B)) != RTA_OK) return st;
+      if ((st = dev_alloc(c, &c->d_c, (size_t)c->Q * c->B)) != RTA_OK) return st;
+      if ((st = dev_alloc(c, &c->fc_done, 1)) != RTA_OK) return st;
     }
     // fused when both store the same spectrum type and the launch's LDS fits
     const int P = c->tier[0].P, C = vec_bins(c->dtype);
@@ -1902,16 +1938,26 @@ int rta_set_feedback(rta_ctx* c, const float* const* fb, const int64_t* lengths,
     if (c->fc_fused && c->lds_fused > 65536)
       HIP_TRY(c, hipFuncSetAttribute(reinterpret_cast<const void*>(block_kernel(c->dtype, c->G)),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_fused));
-  } else {
-    c->fc_fused = false;
   }
+  // serving: the paths belong to the slots; live sources stay, released ones
+  // are freed, as rta_reset does
+  if (c->serve != nullptr) return serve_reset(c);
   return zero_state(c);
+}
+
+int rta_test_feedback_wait(rta_ctx* c, int32_t max_polls, int32_t never_ready) {
+  if (c == nullptr || max_polls < 1 || (never_ready != 0 && never_ready != 1)) return RTA_E_ARG;
+  if (c->poisoned) return RTA_E_DEVICE;
+  c->fc_wait_polls = max_polls;
+  c->fc_wait_bias = never_ready ? 0x40000000u : 0u;
+  return RTA_OK;
 }
 
 int rta_timing_enable(rta_ctx* c, int32_t every) {
   if (c == nullptr || every < 0) return RTA_E_ARG;
   if (every > 0) c->timing_span_read = every;  // spans recorded from now on
   c->timing = every;
+  c->timing_base = c->block;
   c->span_open = false;
   return RTA_OK;
 }
@@ -1930,7 +1976,7 @@ int rta_timing_read(rta_ctx* c, int64_t* blocks, double* block_ms) {
   }
   c->events_used = 0;
   c->span_open = false;
-  return RTA_OK;
+  return device_status(c);
 }
 
 int rta_probe_read(const void* d_buf, int64_t bytes, int32_t grid, float* d_sink, void* stream) {

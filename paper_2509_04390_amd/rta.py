@@ -48,8 +48,8 @@ RTA_MAX_TIERS = 8
 EXPORTED = ("rta_create", "rta_process", "rta_process_device", "rta_reset",
             "rta_query", "rta_timing_enable", "rta_timing_read", "rta_probe_read",
             "rta_destroy", "rta_strerror", "rta_create_tuned", "rta_autotune",
-            "rta_set_feedback", "rta_serve_create", "rta_serve_admit", "rta_serve_release",
-            "rta_serve_query")
+            "rta_set_feedback", "rta_test_feedback_wait", "rta_serve_create", "rta_serve_admit",
+            "rta_serve_release", "rta_serve_query")
 
 
 class rta_scheme(ctypes.Structure):
@@ -78,7 +78,9 @@ class rta_info(ctypes.Structure):
                 ("grid", ctypes.c_int32),
                 ("outputs_per_group", ctypes.c_int32),
                 ("rows_per_item", ctypes.c_int32),
-                ("poisoned", ctypes.c_int32)]
+                ("poisoned", ctypes.c_int32),
+                ("feedback_paths", ctypes.c_int32),
+                ("feedback_fused", ctypes.c_int32)]
 
 
 class rta_tuning(ctypes.Structure):
@@ -129,6 +131,7 @@ _lib.rta_autotune.argtypes = [ctypes.c_double, ctypes.c_int32, ctypes.POINTER(rt
 _lib.rta_process.argtypes = [ctypes.c_void_p, _fp, _fp]
 _lib.rta_set_feedback.argtypes = [ctypes.c_void_p, ctypes.POINTER(_fp),
                                   ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]
+_lib.rta_test_feedback_wait.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]
 _lib.rta_process_device.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_void_p]
 _lib.rta_reset.argtypes = [ctypes.c_void_p]
@@ -152,8 +155,8 @@ _lib.rta_strerror.argtypes = [ctypes.c_int]
 _lib.rta_strerror.restype = ctypes.c_char_p
 for _f in ("rta_create", "rta_process", "rta_process_device", "rta_reset", "rta_query",
            "rta_timing_enable", "rta_timing_read", "rta_probe_read", "rta_destroy",
-           "rta_create_tuned", "rta_autotune", "rta_set_feedback", "rta_serve_create",
-           "rta_serve_admit", "rta_serve_release", "rta_serve_query"):
+           "rta_create_tuned", "rta_autotune", "rta_set_feedback", "rta_test_feedback_wait",
+           "rta_serve_create", "rta_serve_admit", "rta_serve_release", "rta_serve_query"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -282,6 +285,12 @@ def rta_set_feedback(ctx, n_in: int, n_out: int, feedback, spectra="fp32") -> No
     keep, ptrs, lens, _ = _marshal(feedback, n_in, n_out, None, None)
     dtype = DTYPES[spectra] if isinstance(spectra, str) else int(spectra)
     _check(_lib.rta_set_feedback(ctx, ptrs, lens, dtype), "rta_set_feedback")
+
+
+def rta_test_feedback_wait(ctx, max_polls: int, never_ready: bool) -> None:
+    """Bound the fused feedback wait (test aid for its failure path)."""
+    _check(_lib.rta_test_feedback_wait(ctx, int(max_polls), 1 if never_ready else 0),
+           "rta_test_feedback_wait")
 
 
 def rta_reset(ctx) -> None:
@@ -494,6 +503,11 @@ class Server:
 
     def admit(self, filters) -> int:
         return rta_serve_admit(self.ctx, filters)
+
+    def set_feedback(self, feedback, spectra="fp32"):
+        """Feedback paths f_ql from loudspeaker l to slot (microphone) q,
+        n_slots x n_out nested; they stay with the slots."""
+        rta_set_feedback(self.ctx, self.n_slots, self.n_out, feedback, spectra)
 
     def release(self, slot: int) -> None:
         rta_serve_release(self.ctx, slot)

@@ -54,6 +54,7 @@ def test_destroy_null_and_null_handles_are_rejected(rta):
     assert lib.rta_query(None, None) == rta.RTA_E_ARG
     assert lib.rta_timing_enable(None, 1) == rta.RTA_E_ARG
     assert lib.rta_set_feedback(None, None, None, 0) == rta.RTA_E_ARG
+    assert lib.rta_test_feedback_wait(None, 1, 0) == rta.RTA_E_ARG
     assert lib.rta_timing_read(None, None, None) == rta.RTA_E_ARG
     assert lib.rta_create(None, 48000.0, 128, None, 1, 1, None, None, 0, 0) == rta.RTA_E_ARG
     assert lib.rta_create_tuned(None, 48000.0, 128, None, 1, 1, None, None, 0, 0, None) == rta.RTA_E_ARG

@@ -121,3 +121,97 @@ def test_fused_feedback_with_many_microphones_and_long_paths(rta):
     assert np.array_equal(y, y2)
     l_ref, _, _ = oracle.feedback_loop(m, h, f, B)
     check_db(y, l_ref, FP32_DB, "fused feedback 16 mics")
+
+
+def fused_bound(limit, c_ref, mt_ref):
+    """Output error bound with 16-bit synthesis and feedback spectra: the
+    synthesis spectra carry a relative error d, and so does the estimate c,
+    which reaches the output through m - c; the two are independent, so the
+    bound is d * sqrt(1 + g^2), g = rms(c) / rms(m - c) (from the oracle)."""
+    g = np.sqrt(np.mean(c_ref ** 2, axis=1) / np.mean(mt_ref ** 2, axis=1)).max()
+    return limit + 10.0 * np.log10(1.0 + g * g), g
+
+
+@pytest.mark.parametrize("spectra,limit", [("fp16", -60.0), ("bf16", -45.0)])
+def test_fused_feedback_with_16bit_spectra(rta, spectra, limit):
+    """Synthesis and feedback spectra both 16-bit: the feedback convolution
+    runs inside the synthesis launch (the fused 16-bit kernels)."""
+    B, P, L = 32, 2, 3
+    # scales keep the loop gain |F H| well below 1 (|c| / |m - c| about 0.15)
+    h = weak(make_filters(60, [[2500, 900, 0], [700, 2200, 400]]), 0.1)
+    f = weak(make_filters(61, [[400, 250, 600], [0, 500, 150]]), 0.002)
+    m = workloads.white_noise(62, P, 60 * B)
+    with rta.Convolver(h, B, spectra=spectra) as cv:
+        cv.set_feedback(f, spectra=spectra)
+        info = cv.info()
+        assert info["feedback_paths"] == 1 and info["feedback_fused"] == 1
+        y = cv.run(m)
+        cv.reset()
+        y2 = cv.run_device(m)
+    assert np.array_equal(y, y2)
+    l_ref, c_ref, mt_ref = oracle.feedback_loop(m, h, f, B)
+    bound, g = fused_bound(limit, c_ref, mt_ref)
+    say(f"  {spectra}: |c| / |m - c| = {g:.3f}, bound {bound:.1f} dB")
+    check_db(y, l_ref, bound, f"fused feedback {spectra}")
+
+
+@pytest.mark.parametrize("spectra,limit", [("fp32", FP32_DB), ("fp16", -60.0)])
+def test_fused_feedback_64_loudspeakers_16_mics_8192_taps(rta, spectra, limit):
+    """16 microphones -> 64 loudspeakers, feedback paths of 8,192 taps
+    (64 -> 16), block 64, streamed past the feedback length so every feedback
+    partition meets signal; the fused loop against the oracle loop."""
+    B, P, L = 64, 16, 64
+    rng = np.random.default_rng(63)
+    # scales keep the loop gain well below 1 (|c| / |m - c| about 0.17)
+    h = weak(make_filters(64, [[int(rng.integers(200, 1000)) for _ in range(L)] for _ in range(P)]),
+             0.007)
+    f = weak(make_filters(65, [[8192] * L for _ in range(P)], rt60=0.1), 0.002)
+    nb = 8192 // B + 6
+    m = workloads.white_noise(66, P, nb * B)
+    say(f"fused feedback {spectra}: {P} mics x {L} loudspeakers, 8192-tap paths, {nb} blocks")
+    with rta.Convolver(h, B, spectra=spectra) as cv:
+        cv.set_feedback(f, spectra=spectra)
+        assert cv.info()["feedback_fused"] == 1
+        y = cv.run_device(m)
+    l_ref, c_ref, mt_ref = oracle.feedback_loop(m, h, f, B)
+    bound, g = fused_bound(limit, c_ref, mt_ref)
+    say(f"  |c| / |m - c| = {g:.3f}, bound {bound:.1f} dB")
+    check_db(y, l_ref, bound, f"64 -> 16 x 8192 feedback {spectra}")
+
+
+def test_feedback_wait_that_gives_up_fails_the_block(rta):
+    """The synthesis workgroups' wait for the feedback estimate is bounded;
+    forced to give up (an unreachable count, checked from the host), every
+    kernel still finishes, the block reports RTA_E_DEVICE and the context is
+    poisoned."""
+    B = 32
+    h = make_filters(67, [[500, 300]])
+    f = weak(make_filters(68, [[200, 100]]), 0.01)
+    m = workloads.white_noise(69, 1, 4 * B)
+    cv = rta.Convolver(h, B)
+    cv.set_feedback(f)
+    assert cv.info()["feedback_fused"] == 1
+    cv.process(m[:, :B])                       # a normal block first
+    rta.rta_test_feedback_wait(cv.ctx, 64, True)
+    with pytest.raises(rta.RtaError) as e:
+        cv.process(m[:, B:2 * B])
+    assert e.value.status == rta.RTA_E_DEVICE
+    with pytest.raises(rta.RtaError) as e:
+        cv.process(m[:, 2 * B:3 * B])
+    assert e.value.status == rta.RTA_E_DEVICE
+    with pytest.raises(rta.RtaError):
+        cv.info()
+    cv.close()
+    # the device path reports it at the next call
+    import torch
+    cv = rta.Convolver(h, B)
+    cv.set_feedback(f)
+    rta.rta_test_feedback_wait(cv.ctx, 64, True)
+    xi = torch.from_numpy(m[:, :B].copy()).cuda()
+    yo = torch.empty((2, B), dtype=torch.float32, device="cuda")
+    cv.process_device(xi, yo)
+    torch.cuda.synchronize()
+    with pytest.raises(rta.RtaError) as e:
+        cv.process_device(xi, yo)
+    assert e.value.status == rta.RTA_E_DEVICE
+    cv.close()

@@ -120,3 +120,21 @@ def test_nupc_workload_fp16_sampled(rta):
                           rng.integers(0, n, 60)])
     ref = oracle.direct_at(x, filt, idx)
     check_db(y[:, idx], ref, FP16_DB, "nupc workload fp16")
+
+
+def test_nupc_workload_log_sweep_fp16_sampled(rta):
+    """The same batched workload driven by an exponential sine sweep
+    (20 Hz -> 20 kHz) on every source instead of noise."""
+    wl = workloads.config("nupc")
+    wl.signal = "sweep"
+    filt = wl.filters()
+    x = wl.signal_array()
+    say(f"nupc workload, log-sine sweep: blocks={wl.n_blocks}")
+    with rta.Convolver(filt, wl.block, scheme=wl.scheme, spectra="fp16") as cv:
+        y = cv.run_device(x)
+    rng = np.random.default_rng(5)
+    n = x.shape[1]
+    idx = np.unique(np.r_[0, 127, 128, 1919, 1920, 16255, 16256, 16257, n - 1,
+                          rng.integers(0, n, 60)])
+    ref = oracle.direct_at(x, filt, idx)
+    check_db(y[:, idx], ref, FP16_DB, "nupc workload sweep fp16")

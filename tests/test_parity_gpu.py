@@ -240,8 +240,8 @@ def test_autotune_returns_a_tuning_that_matches_the_oracle(rta):
 
 
 def test_block_timing_spans(rta):
-    """rta_timing_enable(every): spans of `every` blocks starting at multiples
-    of it; only complete spans are returned."""
+    """rta_timing_enable(every): spans of `every` blocks, the first starting at
+    the first block after the call; only complete spans are returned."""
     filt = make_filters(5, [[600, 100]])
     x = workloads.white_noise(6, 1, 64 * 40)
     with rta.Convolver(filt, 64) as cv:
@@ -258,3 +258,48 @@ def test_block_timing_spans(rta):
         rta.rta_timing_enable(cv.ctx, 0)
         cv.process(x[:, 21 * 64:22 * 64])
         assert rta.rta_timing_read(cv.ctx) == (0, 0.0)
+        rta.rta_timing_enable(cv.ctx, 4)   # from block 22: span 22-25; 26 open
+        for b in range(22, 27):
+            cv.process(x[:, b * 64:(b + 1) * 64])
+        n, ms = rta.rta_timing_read(cv.ctx)
+        assert n == 4 and ms > 0.0
+        rta.rta_timing_enable(cv.ctx, 0)
+
+
+@pytest.mark.parametrize("spectra,limit", [("fp16", FP16_DB), ("bf16", BF16_DB)])
+def test_main_config_reduced_precision_sampled(rta, spectra, limit):
+    """The main shape (1 -> 32 x 480,000 taps, block 128) with 16-bit spectra,
+    streamed past the filter length so every partition meets input."""
+    wl = workloads.config("main")
+    filt = wl.filters()
+    wl_long = workloads.Workload(**{**wl.__dict__, "n_blocks": 3800})
+    x = wl_long.signal_array()
+    say(f"main config {spectra}: {x.shape[1]} samples")
+    with rta.Convolver(filt, wl.block, spectra=spectra) as cv:
+        y = cv.run_device(x)
+    rng = np.random.default_rng(3)
+    n = x.shape[1]
+    idx = np.unique(np.r_[0, 127, 128, 255, 479999, 480000, n - 1, rng.integers(0, n, 120)])
+    ref = oracle.direct_at(x, filt, idx)
+    check_db(y[:, idx], ref, limit, f"main/{spectra}")
+
+
+@pytest.mark.parametrize("spectra,limit", [("fp32", FP32_DB), ("fp16", FP16_DB)])
+def test_target_point_sampled(rta, spectra, limit):
+    """1 -> 64 loudspeakers x 576,000-tap (12 s) filters at block 128, the
+    launch configuration the benchmark times, streamed past the filter length
+    (4,700 blocks) so every partition meets input; sampled outputs."""
+    wl = workloads.config("target")
+    filt = wl.filters()
+    x = workloads.Workload(**{**wl.__dict__, "n_blocks": 4700}).signal_array()
+    say(f"target point {spectra}: L={wl.n_out} taps={wl.lengths} samples={x.shape[1]}")
+    with rta.Convolver(filt, wl.block, spectra=spectra) as cv:
+        info = cv.info()
+        assert info["tier_count"][0] == 4500
+        y = cv.run_device(x)
+    rng = np.random.default_rng(6)
+    n = x.shape[1]
+    idx = np.unique(np.r_[0, 1, 128, 575999, 576000, n - 1, rng.integers(0, n, 80),
+                          rng.integers(576000, n, 40)])
+    ref = oracle.direct_at(x, filt, idx)
+    check_db(y[:, idx], ref, limit, f"target/{spectra}")

@@ -231,3 +231,48 @@ def test_serve_workload_fp16_sampled(rta):
         x[i, start * B:stop * B] = src[name][1][start * B:stop * B]
     ref = oracle.direct_at(x, [list(src[n][0]) for n in names], idx)
     check_db(y[:, idx], ref, FP16_DB, "serve workload fp16")
+
+
+def weak(filters, scale):
+    return [None if f is None else (f * scale).astype(np.float32) for f in filters]
+
+
+@pytest.mark.parametrize("B,scheme,spectra,limit", [
+    (32, None, "fp32", FP32_DB),
+    (16, [(16, 7), (64, 3), (256, 0)], "fp32", FP32_DB),
+    (32, None, "fp16", FP16_DB)])
+def test_serving_with_feedback_cancellation_matches_oracle(rta, B, scheme, spectra, limit):
+    """Feedback paths fixed per slot (microphone) on a serving context: sources
+    join and leave while each slot's input is its microphone minus the
+    previous block's estimate, and zero while no source is live in it.
+    Against the oracle's serving loop (FP64, block-recursive)."""
+    L, max_taps, n_slots = 4, 2000, 3
+    n_blocks = 200
+    N = n_blocks * B
+    src = make_sources(80, LENS, N)
+    src = {k: (weak(v[0], 0.1), v[1]) for k, v in src.items()}
+    rng = np.random.default_rng(81)
+    fb = [[(0.001 * rng.standard_normal(300) * np.exp(-np.arange(300) / 80.0)).astype(np.float32)
+           for _ in range(L)] for _ in range(n_slots)]
+    events = {0: [("admit", "A")], 3: [("admit", "B")], 6: [("admit", "C")],
+              8: [("admit", "D")], 10: [("release", "A")], 120: [("release", "B")],
+              150: [("release", "D")]}
+    say(f"serve + feedback B={B} scheme={scheme} {spectra}")
+    with rta.Server(n_slots, L, max_taps, B, scheme=scheme, spectra=spectra) as srv:
+        srv.set_feedback(fb, spectra=spectra)
+        info = srv.info()
+        assert info["feedback_paths"] == 1 and info["feedback_fused"] == 1
+        y, rec, refused = run_scenario(rta, srv, src, events, n_blocks, retry=("D",))
+    m = np.zeros((n_slots, N), np.float32)
+    sources = []
+    for name, (q, start, stop) in sorted(rec.items()):
+        stop = n_blocks if stop is None else stop
+        m[q, start * B:stop * B] = src[name][1][start * B:stop * B]
+        sources.append((q, start, stop, src[name][0]))
+    l_ref, c_ref, mt_ref = oracle.serve_loop(m, sources, fb, B)
+    live = np.sum(mt_ref ** 2, axis=1) > 0
+    g = np.sqrt(np.sum(c_ref[live] ** 2, axis=1) / np.sum(mt_ref[live] ** 2, axis=1)).max()
+    bound = limit + 10.0 * np.log10(1.0 + g * g)
+    say(f"  {rec}; |c| / |m - c| = {g:.3f}, bound {bound:.1f} dB")
+    assert g > 0.01, "the feedback estimate must matter"
+    check_db(y, l_ref, bound, f"serving + feedback B={B} {spectra}")
