@@ -40,7 +40,11 @@ namespace rta {
 
 constexpr int kThreads = 256;
 constexpr int kMaxTiers = 8;
-constexpr int kUnroll = 4;  // rows in flight per lane (FP32 spectra; half for 16-bit)
+constexpr int kUnroll = 4;  // rows in flight per lane, FP32 spectra (16-byte loads)
+#ifndef RTA_UNROLL16
+#define RTA_UNROLL16 4
+#endif
+constexpr int kUnroll16 = RTA_UNROLL16;  // rows in flight per lane, 16-bit spectra (8-byte loads)
 
 enum ItemKind : int32_t {
   K_MAC = 0,    // k_block tail: multiply-accumulate of a partition range
@@ -143,10 +147,13 @@ struct KArgs {
 };
 
 // ---------------------------------------------------------------------------
-// Filter-spectrum element loads: C complex bins per 16-byte vector.
+// Filter-spectrum element loads: C = 2 consecutive complex bins per lane and
+// row, one non-temporal load (16 bytes of FP32 spectra, 8 bytes of 16-bit
+// spectra).  Every type thus has the same lane -> bin mapping; the 16-bit
+// types keep twice as many rows in flight for the same bytes.
 // ---------------------------------------------------------------------------
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
 struct f16c_t { uint32_t bits; };   // packed (re, im) FP16 pair
 struct bf16c_t { uint32_t bits; };  // packed (re, im) BF16 pair
@@ -155,60 +162,57 @@ template <typename HT> struct HVec;
 
 template <> struct HVec<float2> {
   static constexpr int C = 2;
-  static __device__ __forceinline__ void load(const float2* p, float2 (&h)[C]) {
-    const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p));
+  static constexpr int U = kUnroll;
+  typedef f32x4 raw_t;
+  static __device__ __forceinline__ raw_t load_raw(const float2* p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p));
+  }
+  static __device__ __forceinline__ void unpack(const raw_t& v, float2 (&h)[C]) {
     h[0] = make_float2(v.x, v.y);
     h[1] = make_float2(v.z, v.w);
   }
   static __device__ __forceinline__ float2 load1(const float2* p) { return *p; }
 };
 
+__device__ __forceinline__ float2 f16pair(uint32_t w) {
+  // the halves are taken apart as scalars: a vector bit_cast of a loaded
+  // word here once made the compiler shrink the load and drop words
+  const _Float16 re = __builtin_bit_cast(_Float16, (uint16_t)(w & 0xffffu));
+  const _Float16 im = __builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
+  return make_float2((float)re, (float)im);
+}
+
+__device__ __forceinline__ float2 bf16pair(uint32_t w) {
+  return make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
+}
+
 template <> struct HVec<f16c_t> {
-  static constexpr int C = 4;
-  static __device__ __forceinline__ void load(const f16c_t* p, float2 (&h)[C]) {
-    const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
-    // Each 32-bit word is one (re, im) pair.  The halves are taken apart as
-    // scalars: a vector bit_cast of v[j] here makes the compiler drop three
-    // of the four words of the load.
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const uint32_t w = v[j];
-      const _Float16 re = __builtin_bit_cast(_Float16, (uint16_t)(w & 0xffffu));
-      const _Float16 im = __builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
-      h[j] = make_float2((float)re, (float)im);
-    }
+  static constexpr int C = 2;
+  static constexpr int U = kUnroll16;
+  typedef u32x2 raw_t;
+  static __device__ __forceinline__ raw_t load_raw(const f16c_t* p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(p));
   }
-  static __device__ __forceinline__ float2 load1(const f16c_t* p) {
-    const uint32_t w = p->bits;
-    const _Float16 re = __builtin_bit_cast(_Float16, (uint16_t)(w & 0xffffu));
-    const _Float16 im = __builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
-    return make_float2((float)re, (float)im);
+  static __device__ __forceinline__ void unpack(const raw_t& v, float2 (&h)[C]) {
+    h[0] = f16pair(v.x);
+    h[1] = f16pair(v.y);
   }
+  static __device__ __forceinline__ float2 load1(const f16c_t* p) { return f16pair(p->bits); }
 };
 
 template <> struct HVec<bf16c_t> {
-  static constexpr int C = 4;
-  static __device__ __forceinline__ void load(const bf16c_t* p, float2 (&h)[C]) {
-    const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      h[j] = make_float2(__uint_as_float(v[j] << 16), __uint_as_float(v[j] & 0xffff0000u));
+  static constexpr int C = 2;
+  static constexpr int U = kUnroll16;
+  typedef u32x2 raw_t;
+  static __device__ __forceinline__ raw_t load_raw(const bf16c_t* p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(p));
   }
-  static __device__ __forceinline__ float2 load1(const bf16c_t* p) {
-    const uint32_t w = p->bits;
-    return make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
+  static __device__ __forceinline__ void unpack(const raw_t& v, float2 (&h)[C]) {
+    h[0] = bf16pair(v.x);
+    h[1] = bf16pair(v.y);
   }
+  static __device__ __forceinline__ float2 load1(const bf16c_t* p) { return bf16pair(p->bits); }
 };
-
-template <int C>
-__device__ __forceinline__ void load_x(const float2* p, float2 (&x)[C]) {
-#pragma unroll
-  for (int j = 0; j < C; j += 2) {
-    const f32x4 v = *reinterpret_cast<const f32x4*>(p + j);
-    x[j] = make_float2(v.x, v.y);
-    x[j + 1] = make_float2(v.z, v.w);
-  }
-}
 
 __device__ __forceinline__ int wrap_slot(int64_t v, int K) {
   int s = (int)(v % K);
@@ -261,48 +265,41 @@ __device__ void mac_item(int Qn, const DevTier& T, const Item& it,
   const int step = RP % K;
   int p = it.p0 + s;
   int slot = wrap_slot(frame - p, K);
-  // 16-bit spectra carry twice the bins per load; with a quarter of the rows
-  // in flight the registers stay low enough for every tail workgroup of the
-  // launch to be resident at once (measured: with half, some started only
-  // when others finished and the launch took 24 us instead of 18 us)
-  constexpr int U = C == 2 ? kUnroll : kUnroll / 4;
+  // U rows in flight per lane: every load of a pass is issued before any
+  // is used (raw registers), then the pass is accumulated
+  constexpr int U = HVec<HT>::U;
+  typedef typename HVec<HT>::raw_t raw_t;
   for (; p < it.p1; p += RP * U) {
-    float2 xv[U][C];
-    float2 hv[U][G][C];
+    f32x4 xr[U];
+    raw_t hr[U][G];
     int sl = slot;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int pu = p + u * RP;
-      if (pu < it.p1) {
-        load_x<C>(Xq + (int64_t)sl * P, xv[u]);
-      } else {
+      xr[u] = pu < it.p1 ? *reinterpret_cast<const f32x4*>(Xq + (int64_t)sl * P) : f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int j = 0; j < C; ++j) xv[u][j] = make_float2(0.f, 0.f);
-      }
-#pragma unroll
-      for (int g = 0; g < G; ++g) {
-        if (pu < pend[g]) {
-          HVec<HT>::load(hb[g] + (int64_t)pu * P, hv[u][g]);
-        } else {
-#pragma unroll
-          for (int j = 0; j < C; ++j) hv[u][g][j] = make_float2(0.f, 0.f);
-        }
-      }
+      for (int g = 0; g < G; ++g)
+        hr[u][g] = pu < pend[g] ? HVec<HT>::load_raw(hb[g] + (int64_t)pu * P) : raw_t{};
       sl -= step;
       if (sl < 0) sl += K;
     }
     slot = sl;
 #pragma unroll
-    for (int u = 0; u < U; ++u)
+    for (int u = 0; u < U; ++u) {
+      const float2 xv[C] = {make_float2(xr[u].x, xr[u].y), make_float2(xr[u].z, xr[u].w)};
 #pragma unroll
-      for (int g = 0; g < G; ++g)
+      for (int g = 0; g < G; ++g) {
+        float2 hv[C];
+        HVec<HT>::unpack(hr[u][g], hv);
 #pragma unroll
         for (int j = 0; j < C; ++j) {
-          acc[g][j][0] += hv[u][g][j].x * xv[u][j].x;   // Re H Re X
-          acc[g][j][1] += hv[u][g][j].y * xv[u][j].y;   // Im H Im X
-          acc[g][j][2] += hv[u][g][j].x * xv[u][j].y;   // Re H Im X
-          acc[g][j][3] += hv[u][g][j].y * xv[u][j].x;   // Im H Re X
+          acc[g][j][0] += hv[j].x * xv[j].x;   // Re H Re X
+          acc[g][j][1] += hv[j].y * xv[j].y;   // Im H Im X
+          acc[g][j][2] += hv[j].x * xv[j].y;   // Re H Im X
+          acc[g][j][3] += hv[j].y * xv[j].x;   // Im H Re X
         }
+      }
+    }
   }
 
   // combine the four real sums; packed bin 0 holds two real products

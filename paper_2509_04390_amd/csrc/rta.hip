@@ -217,7 +217,7 @@ int dev_alloc(rta_ctx* c, T** p, size_t count) {
 }
 
 size_t spectra_elem_bytes(int dtype) { return dtype == RTA_FP32 ? 8 : 4; }
-int vec_bins(int dtype) { return dtype == RTA_FP32 ? 2 : 4; }
+int vec_bins(int) { return 2; }  // bins per lane and row in the multiply-accumulate (HVec<>::C)
 
 // W_P^j (j < P) then W_2P^k (k < P), FP64 evaluated then rounded to FP32.
 std::vector<float2> twiddles(int P) {
