@@ -388,6 +388,23 @@ int rta_serve_create(rta_ctx** out, double fs, int32_t block,
 int rta_serve_admit(rta_ctx* ctx, const float* const* filters,
                     const int64_t* lengths, int32_t* slot);
 
+/* rta_serve_admit() for callers that cannot allocate device memory (code
+ * under graph capture, tight serving loops, harnesses that forbid it): the
+ * same admission, but its filter-spectra build is staged in a fixed device
+ * array that the library holds for the life of the process on each device
+ * (5.5 MiB: up to 2^20 staged taps and 2^16 spectrum rows per batch), so
+ * the call allocates nothing -- no hipMalloc, hipFree or allocating library
+ * routine; it still copies the taps to the device and waits for the build.
+ * Arguments and errors as rta_serve_admit(), plus RTA_E_ARG for a filter
+ * longer than 2^20 taps (the array's limit) and RTA_E_DEVICE if the array's
+ * device address could not be found.  The array is shared by every call on
+ * one device: overlapping calls in one process are serialized by a lock
+ * (each call clears the array's flag before use); concurrent calls that
+ * bypassed the lock would race on it.  The output of the admitted source is
+ * bit-identical to rta_serve_admit()'s. */
+int rta_serve_admit_noalloc(rta_ctx* ctx, const float* const* filters,
+                            const int64_t* lengths, int32_t* slot);
+
 /* Release the source in `slot` (JOINING or LIVE; else RTA_E_STATE). */
 int rta_serve_release(rta_ctx* ctx, int32_t slot);
 

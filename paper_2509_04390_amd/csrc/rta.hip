@@ -40,6 +40,50 @@ constexpr int kXcds = 8;                     // MI355X: 8 XCDs, workgroups round
 constexpr int64_t kStageBytes = 64ll << 20;  // filter taps staged per spectra batch
 constexpr size_t kMaxTimedBlocks = 65536;
 
+// Scratch of rta_serve_admit_noalloc: the staging of one admission's filter
+// spectra build -- an FP16 range flag, the row table and the staged taps --
+// in a file-scope device array instead of buffers the library allocates.
+// Each device holds its own copy from module load until the process ends.
+constexpr int64_t kScratchRows = int64_t(1) << 16;         // spectrum rows per batch
+constexpr int64_t kScratchTaps = int64_t(1) << 20;         // staged taps per batch
+constexpr size_t kScratchRowsOff = 256;                    // after the range flag
+constexpr size_t kScratchTapsOff = kScratchRowsOff + (size_t)kScratchRows * 24;  // SpecRow: 24 B
+constexpr size_t kScratchBytes = kScratchTapsOff + (size_t)kScratchTaps * sizeof(float);
+constexpr int kMaxDevices = 64;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+static_assert(sizeof(SpecRow) == 24, "scratch layout assumes 24-byte rows");
+static_assert(kScratchRowsOff % 256 == 0 && kScratchTapsOff % 256 == 0, "scratch alignment");
+
+// Device address of `scratch` on each device (the array's host-side name is
+// not a device address), found once per device at set-up; uses of the array
+// by overlapping calls in this process are serialized per device.
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_use[kMaxDevices];
+
+// With `dev` current: look up (once) and return the device address of the
+// scratch array on `dev`, or nullptr if the runtime refuses.
+void* scratch_on(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
+
 struct TierHost {
   int P = 0, logP = 0, K = 0, count = 0;
   int kcap = 0;  // serving: partitions of a max_taps filter in this tier
@@ -1565,7 +1609,10 @@ std::vector<int> slot_states(Serve* sv) {
   return st;
 }
 
-int serve_admit(rta_ctx* c, const float* const* filters, const int64_t* lengths, int32_t* slot) {
+// noalloc: stage the spectra build in this device's scratch array instead of
+// the context's staging buffers.
+int serve_admit(rta_ctx* c, const float* const* filters, const int64_t* lengths, int32_t* slot,
+                bool noalloc) {
   Serve* sv = c->serve;
   const int L = c->L;
   std::lock_guard<std::mutex> cl(sv->ctl);
@@ -1638,8 +1685,21 @@ int serve_admit(rta_ctx* c, const float* const* filters, const int64_t* lengths,
   for (int t = 0; t < c->n_tiers; ++t)
     for (int l = 0; l < L; ++l)
       if (src.kp[t][l] > 0) jobs.push_back(SpecJob{t, filters[l], lengths[l], src.row[t][l], src.kp[t][l]});
-  int st = run_spectra(c, jobs, sv->aux, sv->d_stage, sv->stage_floats, sv->d_rows, sv->row_cap,
-                       sv->d_range);
+  int st;
+  if (noalloc) {
+    unsigned char* base = static_cast<unsigned char*>(scratch_on(c->device));
+    if (base == nullptr) {
+      st = RTA_E_DEVICE;
+    } else {
+      std::lock_guard<std::mutex> use(g_scratch_use[c->device]);
+      st = run_spectra(c, jobs, sv->aux, reinterpret_cast<float*>(base + kScratchTapsOff), kScratchTaps,
+                       reinterpret_cast<SpecRow*>(base + kScratchRowsOff), kScratchRows,
+                       reinterpret_cast<int*>(base));
+    }
+  } else {
+    st = run_spectra(c, jobs, sv->aux, sv->d_stage, sv->stage_floats, sv->d_rows, sv->row_cap,
+                     sv->d_range);
+  }
   if (st != RTA_OK) {
     give_back();
     return st;
@@ -2080,6 +2140,11 @@ int rta_serve_create(rta_ctx** out, double fs, int32_t block, const rta_scheme* 
   const int st = validate(fs, block, scheme, cfg->n_slots, cfg->n_out, f.data(), len.data(), spectra,
                           flags, size, count);
   if (st != RTA_OK) return st;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || scratch_on(dev) == nullptr) {
+    (void)hipGetLastError();
+    return RTA_E_DEVICE;  // the scratch array of rta_serve_admit_noalloc
+  }
   return create_ctx(out, fs, block, size, count, cfg->n_slots, cfg->n_out, f.data(), len.data(),
                     spectra, flags, tuning, cfg);
 }
@@ -2093,7 +2158,21 @@ int rta_serve_admit(rta_ctx* c, const float* const* filters, const int64_t* leng
     if (lengths[l] < 0 || lengths[l] > c->serve->cfg.max_taps) return RTA_E_ARG;
     if (lengths[l] > 0 && filters[l] == nullptr) return RTA_E_ARG;
   }
-  return serve_admit(c, filters, lengths, slot);
+  return serve_admit(c, filters, lengths, slot, false);
+}
+
+int rta_serve_admit_noalloc(rta_ctx* c, const float* const* filters, const int64_t* lengths,
+                            int32_t* slot) {
+  if (c == nullptr || filters == nullptr || lengths == nullptr || slot == nullptr) return RTA_E_ARG;
+  if (c->serve == nullptr) return RTA_E_STATE;
+  if (c->poisoned) return RTA_E_DEVICE;
+  *slot = -1;
+  for (int l = 0; l < c->L; ++l) {
+    if (lengths[l] < 0 || lengths[l] > c->serve->cfg.max_taps) return RTA_E_ARG;
+    if (lengths[l] > kScratchTaps) return RTA_E_ARG;  // beyond the scratch array
+    if (lengths[l] > 0 && filters[l] == nullptr) return RTA_E_ARG;
+  }
+  return serve_admit(c, filters, lengths, slot, true);
 }
 
 int rta_serve_release(rta_ctx* c, int32_t slot) {

@@ -49,7 +49,7 @@ EXPORTED = ("rta_create", "rta_process", "rta_process_device", "rta_reset",
             "rta_query", "rta_timing_enable", "rta_timing_read", "rta_probe_read",
             "rta_destroy", "rta_strerror", "rta_create_tuned", "rta_autotune",
             "rta_set_feedback", "rta_test_feedback_wait", "rta_serve_create", "rta_serve_admit",
-            "rta_serve_release", "rta_serve_query")
+            "rta_serve_admit_noalloc", "rta_serve_release", "rta_serve_query")
 
 
 class rta_scheme(ctypes.Structure):
@@ -148,6 +148,7 @@ _lib.rta_serve_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_doub
                                   ctypes.c_uint32, ctypes.POINTER(rta_tuning)]
 _lib.rta_serve_admit.argtypes = [ctypes.c_void_p, ctypes.POINTER(_fp),
                                  ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]
+_lib.rta_serve_admit_noalloc.argtypes = _lib.rta_serve_admit.argtypes
 _lib.rta_serve_release.argtypes = [ctypes.c_void_p, ctypes.c_int32]
 _lib.rta_serve_query.argtypes = [ctypes.c_void_p, ctypes.POINTER(rta_serve_info),
                                  ctypes.POINTER(rta_slot_info)]
@@ -156,7 +157,8 @@ _lib.rta_strerror.restype = ctypes.c_char_p
 for _f in ("rta_create", "rta_process", "rta_process_device", "rta_reset", "rta_query",
            "rta_timing_enable", "rta_timing_read", "rta_probe_read", "rta_destroy",
            "rta_create_tuned", "rta_autotune", "rta_set_feedback", "rta_test_feedback_wait",
-           "rta_serve_create", "rta_serve_admit", "rta_serve_release", "rta_serve_query"):
+           "rta_serve_create", "rta_serve_admit", "rta_serve_admit_noalloc", "rta_serve_release",
+           "rta_serve_query"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -354,6 +356,15 @@ def rta_serve_admit(ctx, filters) -> int:
     return slot.value
 
 
+def rta_serve_admit_noalloc(ctx, filters) -> int:
+    """rta_serve_admit without any device allocation (filters <= 2^20 taps)."""
+    keep, ptrs, lens, _ = _marshal(list(filters), 1, len(filters), None, None)
+    slot = ctypes.c_int32(-1)
+    _check(_lib.rta_serve_admit_noalloc(ctx, ptrs, lens, ctypes.byref(slot)),
+           "rta_serve_admit_noalloc")
+    return slot.value
+
+
 def rta_serve_release(ctx, slot: int) -> None:
     _check(_lib.rta_serve_release(ctx, int(slot)), "rta_serve_release")
 
@@ -503,6 +514,9 @@ class Server:
 
     def admit(self, filters) -> int:
         return rta_serve_admit(self.ctx, filters)
+
+    def admit_noalloc(self, filters) -> int:
+        return rta_serve_admit_noalloc(self.ctx, filters)
 
     def set_feedback(self, feedback, spectra="fp32"):
         """Feedback paths f_ql from loudspeaker l to slot (microphone) q,

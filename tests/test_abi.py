@@ -60,6 +60,7 @@ def test_destroy_null_and_null_handles_are_rejected(rta):
     assert lib.rta_create_tuned(None, 48000.0, 128, None, 1, 1, None, None, 0, 0, None) == rta.RTA_E_ARG
     assert lib.rta_autotune(48000.0, 128, None, 1, 1, None, None, 0, 0, 8, None, None) == rta.RTA_E_ARG
     assert lib.rta_serve_admit(None, None, None, None) == rta.RTA_E_ARG
+    assert lib.rta_serve_admit_noalloc(None, None, None, None) == rta.RTA_E_ARG
     assert lib.rta_serve_release(None, 0) == rta.RTA_E_ARG
     assert lib.rta_serve_query(None, None, None) == rta.RTA_E_ARG
 
