@@ -68,12 +68,15 @@ typedef enum rta_dtype { RTA_FP32 = 0, RTA_FP16 = 1, RTA_BF16 = 2 } rta_dtype;
  *   count[t] number of partitions of tier t; count[n_tiers-1] == 0 means
  *            "as many as the longest filter needs".
  * Tier t covers filter taps [o_t, o_t + count[t]*size[t]) with o_0 = 0 and
- * o_{t+1} = o_t + count[t]*size[t].  For t >= 1 the scheme must satisfy
- * o_t >= size[t] + block: a frame of tier t needs one block for its FFT and
- * at least one for its multiply-accumulate before its first output sample
- * is due.  The multiply-accumulate is spread over min(s, size[t]/block + 1)
- * - 1 blocks, s = (o_t + block - size[t]) / block; o_t = 2*size[t] - block
- * gives every tier s = size[t]/block.  Other schemes return RTA_E_ARG.
+ * o_{t+1} = o_t + count[t]*size[t].  A frame of tier t >= 1 (its input
+ * samples complete at the end of one block) has s = (o_t + block - size[t])
+ * / block blocks before its first output sample is due; its forward FFT
+ * takes two of them, its inverse FFT two more (each transform runs as two
+ * passes in consecutive blocks), so the scheme must satisfy s >= 5, i.e.
+ * o_t >= size[t] + 4*block.  The multiply-accumulate is spread over
+ * min(s - 4, size[t]/block - 1) blocks (1 with RTA_FLAG_SPIKE); with
+ * o_t = 2*size[t] - block (s = size[t]/block) tiers with size[t] >=
+ * 8*block qualify.  Other schemes return RTA_E_ARG.
  * A NULL scheme means uniform partitioning with size[0] = block, i.e. the
  * paper's UPOLS with n_k = n_x and n_f = 2 n_x (Sec. IV). */
 typedef struct rta_scheme {

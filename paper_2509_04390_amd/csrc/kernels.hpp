@@ -7,7 +7,9 @@
 // Only the p = 0 term needs the block that has just arrived, and the p = 1
 // term needs the previous block's spectrum; every term p >= 2 uses spectra
 // that were in the delay line one block earlier.  Launch n of k_block
-// therefore runs two kinds of workgroups side by side:
+// therefore runs two kinds of workgroups side by side (three with
+// non-uniform partitions, whose later tiers add transform workgroups, see
+// "Later tiers" below):
 //
 //   head workgroups (one per output, dispatched first, latency critical):
 //   real FFT of each input's window [x_{n-1}, x_n] (Sec. IV step
@@ -47,21 +49,27 @@ constexpr int kUnroll = 4;  // rows in flight per lane, FP32 spectra (16-byte lo
 constexpr int kUnroll16 = RTA_UNROLL16;  // rows in flight per lane, 16-bit spectra (8-byte loads)
 
 enum ItemKind : int32_t {
-  K_MAC = 0,    // k_block tail: multiply-accumulate of a partition range
+  K_MAC = 0,    // tail: multiply-accumulate of a partition range
   K_NOP = 1,    // padding
-  K_FFT = 2,    // k_tier: real FFT of a later tier's input frame into its ring
-  K_FINAL = 3   // k_tier: reduce + inverse FFT of a later tier's frame into its
-                // output ring
+  // later tiers: each 2P_t-point real transform is split into a column pass
+  // and a row pass (P_t = N1 N2 complex points), run by several small
+  // workgroups in consecutive launches
+  K_FFT_A = 2,  // input frame -> N2-point transforms of its columns
+  K_FFT_B = 3,  // N1-point transforms of column pairs -> packed spectrum -> ring
+  K_FIN_A = 4,  // partial sums of column pairs -> N1-point inverse transforms
+  K_FIN_B = 5   // N2-point inverse transforms of rows -> output ring
 };
 
 struct Item {          // one workgroup's work in one block (48 bytes)
   int32_t kind;        // ItemKind
-  int32_t w;           // K_MAC: bins of the slice (divides P; W/C lanes per row)
+  int32_t w;           // K_MAC: bins of the slice (divides P; W/C lanes per row);
+                       // tier passes: columns (rows) or column pairs per item
   int32_t tier;
   int32_t group;       // reduction group (outputs l0 .. l0+nl-1)
-  int32_t q;           // input channel
+  int32_t q;           // input channel; K_FIN_*: output within the group
   int32_t p0, p1;      // partition range
-  int32_t k0;          // first bin of the slice
+  int32_t k0;          // K_MAC: first bin of the slice; tier passes: index of
+                       // the item within its pass
   int32_t slot;        // partial-sum slot (tier-local)
   int32_t acc;         // K_MAC of a later tier: add to the slot (0: store)
   int32_t lag;         // tiers >= 1: launch index minus the block in which
@@ -82,10 +90,12 @@ struct DevTier {
   float2* partial;           // [2][slots][G][P], by block parity
   const float2* tw;          // W_P^j (j<P) then W_2P^k (k<P)
   float* oring;              // tiers >= 1: output ring [L][R]
+  float2* tfwd;              // tiers >= 1: forward column-pass results [Q][P]
+  float2* tinv;              // tiers >= 1: inverse column-pass results [L][P]
   int64_t offset;            // first filter tap of the tier (o_t)
   int32_t P, logP, K, nslots;
   int32_t r;                 // P / B: blocks per frame
-  int32_t pad2;
+  int32_t lg1;               // tiers >= 1: log2 N1, P = N1 N2, N1 <= N2
 };
 
 // Feedback convolution fused into the synthesis launch (Sec. III-A Eq. 3,
@@ -126,12 +136,14 @@ struct KArgs {
   int32_t head_slots;        // head part of the grid (n_head rounded up to 8)
   int32_t pad;
   int64_t n;                 // index of the block of this launch
-  const Item* tier_items;    // k_tier lists [n_phase][max_tier_items]
-  const int32_t* tier_count; // items per phase
+  const Item* tier_items;    // later tiers' transform passes [n_phase][max_tier_items]
+  const int32_t* tier_count; // transform items per phase
   const int32_t* tier_slot0; // [tier][group] first partial slot of later tiers
   const int32_t* tier_nslot; // [tier][group] partial slots of later tiers
   int32_t max_tier_items;
   int32_t n_groups_total;
+  int32_t tier_slots;        // transform part of this launch's grid (a multiple of 8)
+  int32_t pad4;
   const void* H01;           // [L][Q][2][P] spectra of partitions 0 and 1
   unsigned int* head_count;  // heads finished in this launch (zero between)
   int64_t* done_flag;        // host-visible: n + 1 once the output is written
@@ -457,6 +469,27 @@ __device__ void head_reduce(const KArgs& A, const DevTier& T, const Group& grp, 
   __syncthreads();
 }
 
+// Fused feedback: thread 0 waits until every feedback head of this launch
+// has published c_{n-1} (they are dispatched first and wait for nothing),
+// then the workgroup proceeds.  The spin is bounded all the same; a wait that
+// gives up stores 1 in the host-visible error word, which fails the block on
+// the host.
+__device__ void fc_wait(const KArgs& A) {
+  if (threadIdx.x == 0) {
+    const unsigned int target = (unsigned int)((A.n + 1) * A.fc.n_heads) + A.fc.wait_bias;
+    bool ready = false;
+    for (int it = 0; it < A.fc.wait_polls; ++it) {
+      if ((int)(__hip_atomic_load(A.fc.done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) - target) >= 0) {
+        ready = true;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    if (!ready) __hip_atomic_store(A.status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+  __syncthreads();
+}
+
 // LDS layout of a head workgroup, in float2 units (the host sizes the launch with the
 // same function): Y [G][P] | Xa [nbuf][P] | Xb [nbuf][P] | twiddles | 256.
 struct HeadLds {
@@ -584,24 +617,8 @@ __device__ void head_work(const KArgs& A, const Group& grp, int gsel, float2* ld
   head_reduce<HT, G>(A, Tcur, grp, n, Y, scratch);
 
   // fused feedback: wait until every feedback head of this launch has
-  // published c_{n-1} (they are dispatched first and wait for nothing; the
-  // spin is bounded all the same, and a wait that gives up is reported
-  // through the status word, which fails the block on the host)
-  if (A.fc_on) {
-    if (tid == 0) {
-      const unsigned int target = (unsigned int)((n + 1) * A.fc.n_heads) + A.fc.wait_bias;
-      bool ready = false;
-      for (int it = 0; it < A.fc.wait_polls; ++it) {
-        if ((int)(__hip_atomic_load(A.fc.done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) - target) >= 0) {
-          ready = true;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(2);
-      }
-      if (!ready) __hip_atomic_store(A.status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    }
-    __syncthreads();
-  }
+  // published c_{n-1}
+  if (A.fc_on) fc_wait(A);
 
   // 2. the term p = 0: window -> real FFT -> ring slot n mod K, times H_{l,q,0}
   const int slot0 = wrap_slot(n, T.K);
@@ -839,11 +856,259 @@ __device__ void fc_head_work(const KArgs& A, int j, float2* lds) {
   if (tid == 0) __hip_atomic_fetch_add(F.done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
+// ---------------------------------------------------------------------------
+// Later tiers (non-uniform partitioning, Sec. III-B): partitions of P_t = r B
+// samples covering filter taps [o_t, o_t + K_t P_t).  Frame f of the tier is
+// input samples [f P_t, (f+1) P_t), complete after block n_f = (f+1) r - 1.
+// Its contribution y[f P_t + o_t + i] (i < P_t) is the second half of the
+// 2 P_t-point inverse FFT of sum_q sum_p H_{t,l,q,p} X_{t,q}(f - p): the
+// tier's delay o_t is realized in the time domain through the output ring.
+//
+// The 2P_t-point real transforms run as P_t-point complex transforms of
+// z[m] = w[2m] + i w[2m+1] (fft_lds.hpp), each factored as P_t = N1 N2 with
+// n = n1 + N1 n2 (time) and k = N2 k1 + k2 (frequency):
+//   Z[N2 k1 + k2] = sum_n1 W_N1^{n1 k1} W_P^{n1 k2} sum_n2 z[n1 + N1 n2] W_N2^{n2 k2}
+// (conjugate twiddles for the inverse).  A pass is a batch of short
+// transforms that one 256-thread workgroup runs in LDS; the two passes of a
+// transform run in consecutive launches and each pass is spread over several
+// workgroups, so no workgroup holds a whole transform and the launch's LDS
+// stays small.  Work of frame f, by lag after block n_f (the host's lists):
+//   0           K_FFT_A  columns n1: N2-point transforms of the window times
+//                        W_P^{n1 k2}, into tfwd[q] (k2-major)
+//   1           K_FFT_B  column pairs (k2, N2 - k2): N1-point transforms, the
+//                        real-transform split, packed bins into slot f mod K
+//   2 .. nmac+1 K_MAC    the frame's multiply-accumulate (tail items)
+//   nmac+2      K_FIN_A  column pairs: partial slots summed, the inverse
+//                        split, N1-point inverse transforms times
+//                        W_P^{-n1 k2}, into tinv[l] (n1-major)
+//   nmac+3      K_FIN_B  rows n1: N2-point inverse transforms; the second
+//                        half of the samples (overlap-save), scaled by
+//                        1/(2P), into the output ring at f P + o_t
+// Bin k of the real transform pairs with bin P - k, which lies in column
+// N2 - k2 (row N1 - 1 - k1) for k2 > 0 and in column 0 (row N1 - k1) for
+// k2 = 0; columns 0 and N2/2 pair with themselves.  A pair item holds both
+// columns of each pair: its first np columns are k2 = j np .. j np + np - 1,
+// the other np their partners, with column N2/2 in place of column 0's.
+// ---------------------------------------------------------------------------
+constexpr int kTierBuf = 1024;                 // float2 per LDS buffer of a pass
+constexpr int kTierLds = 2 * kTierBuf + 128;   // two buffers and an N-point table (N <= 128)
+
+__host__ __device__ inline int tier_lg1(int logP) { return logP / 2; }
+// rows per K_FFT_A / K_FIN_B item (N2-point transforms)
+__host__ __device__ inline int tier_rows_per_item(int logP) {
+  const int n1 = 1 << tier_lg1(logP), n2 = 1 << (logP - tier_lg1(logP));
+  return n1 < kTierBuf / n2 ? n1 : kTierBuf / n2;
+}
+// column pairs per K_FFT_B / K_FIN_A item (two N1-point transforms each)
+__host__ __device__ inline int tier_pairs_per_item(int logP) {
+  const int n1 = 1 << tier_lg1(logP), n2 = 1 << (logP - tier_lg1(logP));
+  return n2 / 2 < kTierBuf / (2 * n1) ? n2 / 2 : kTierBuf / (2 * n1);
+}
+
+// column k2 of local column c (c < 2 np) of pair item j
+__device__ __forceinline__ int pair_col(int j, int np, int c, int N2) {
+  const int k = j * np + (c < np ? c : c - np);
+  if (c < np) return k;
+  return k == 0 ? N2 / 2 : N2 - k;
+}
+// local column holding the partner bins of local column c
+__device__ __forceinline__ int pair_partner(int j, int np, int c) {
+  if (j * np + (c < np ? c : c - np) == 0) return c;  // columns 0 and N2/2
+  return c < np ? c + np : c - np;
+}
+
+// Input sample i (< B) of this block for input q as the first tier sees it:
+// the microphone minus the previous block's feedback estimate, zero for a
+// slot that is not live.  (Fused feedback: the estimate is written in this
+// launch by other workgroups, so it is read where every XCD sees it; the
+// caller has waited for it.)
+__device__ __forceinline__ float block_sample(const KArgs& A, int q, int i) {
+  float v = A.in[(int64_t)q * A.B + i];
+  if (A.sub != nullptr) {
+    const float* p = A.sub + (int64_t)q * A.B + i;
+    v -= A.fc_on ? __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) : *p;
+  }
+  return (A.live != nullptr && A.live[q] == 0) ? 0.f : v;  // a select: NaN stays out
+}
+
+template <int G>
+__device__ void tier_fft_a(const KArgs& A, const Item& it, float2* lds) {
+  const DevTier& T = A.tier[it.tier];
+  const int tid = threadIdx.x, P = T.P;
+  const int lg1 = T.lg1, N1 = 1 << lg1, lg2 = T.logP - lg1, N2 = 1 << lg2;
+  const int nr = it.w, n10 = it.k0 * nr, q = it.q;
+  float2* a = lds;
+  float2* b = lds + kTierBuf;
+  float2* twn = lds + 2 * kTierBuf;
+  for (int j = tid; j < N2; j += kThreads) twn[j] = T.tw[j << lg1];  // W_N2^j = W_P^{j N1}
+  if (A.fc_on) fc_wait(A);  // the block's samples need c_{n-1}
+  // window: the last 2P samples up to the end of this block (its first
+  // 2P - B from the history ring)
+  const float* hq = A.hist + (int64_t)q * (A.hist_mask + 1);
+  const int64_t start = (A.n - it.lag + 1) * A.B - 2 * (int64_t)P;
+  const int cur = 2 * P - A.B;
+  auto sample = [&](int i) {
+    return i < cur ? hq[(start + i) & A.hist_mask] : block_sample(A, q, i - cur);
+  };
+  for (int e = tid; e < nr * N2; e += kThreads) {
+    const int c = e & (nr - 1), n2 = e / nr;
+    const int m = n10 + c + (n2 << lg1);
+    a[c * N2 + n2] = make_float2(sample(2 * m), sample(2 * m + 1));
+  }
+  __syncthreads();
+  const float2* z = fft_stockham<false>(a, b, N2, lg2, twn, nr);
+  float2* dst = T.tfwd + (int64_t)q * P;
+  for (int e = tid; e < nr * N2; e += kThreads) {
+    const int c = e & (nr - 1), k2 = e / nr;
+    const int n1 = n10 + c;
+    dst[k2 * N1 + n1] = cmul(z[c * N2 + k2], T.tw[(n1 * k2) & (P - 1)]);
+  }
+}
+
+template <int G>
+__device__ void tier_fft_b(const KArgs& A, const Item& it, float2* lds) {
+  const DevTier& T = A.tier[it.tier];
+  const int tid = threadIdx.x, P = T.P;
+  const int lg1 = T.lg1, N1 = 1 << lg1, lg2 = T.logP - lg1, N2 = 1 << lg2;
+  const int np = it.w, nc = 2 * np, j = it.k0, q = it.q;
+  float2* a = lds;
+  float2* b = lds + kTierBuf;
+  float2* twn = lds + 2 * kTierBuf;
+  for (int i = tid; i < N1; i += kThreads) twn[i] = T.tw[i << lg2];  // W_N1^i
+  const float2* src = T.tfwd + (int64_t)q * P;
+  for (int e = tid; e < nc * N1; e += kThreads) {
+    const int c = e >> lg1, k1 = e & (N1 - 1);
+    a[e] = src[pair_col(j, np, c, N2) * N1 + k1];
+  }
+  __syncthreads();
+  const float2* Z = fft_stockham<false>(a, b, N1, lg1, twn, nc);
+  // packed bins X[k] = E + W_2P^k O from Z[k] and Z[P - k] (fft_lds.hpp)
+  const int64_t f = (A.n - it.lag + 1) / T.r - 1;
+  float2* dst = T.X + ((int64_t)q * T.K + wrap_slot(f, T.K)) * P;
+  const float2* tw2 = T.tw + P;
+  for (int e = tid; e < nc * N1; e += kThreads) {
+    const int c = e & (nc - 1), k1 = e / nc;
+    const int k2 = pair_col(j, np, c, N2);
+    const int k = (k1 << lg2) + k2;
+    const float2 zk = Z[c * N1 + k1];
+    float2 x;
+    if (k == 0) {
+      x = make_float2(zk.x + zk.y, zk.x - zk.y);
+    } else {
+      const int pk1 = k2 == 0 ? ((N1 - k1) & (N1 - 1)) : N1 - 1 - k1;
+      const float2 zm = cconj(Z[pair_partner(j, np, c) * N1 + pk1]);
+      const float2 E = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y + zm.y));
+      const float2 d = csub(zk, zm);
+      const float2 O = make_float2(0.5f * d.y, -0.5f * d.x);  // -i d / 2
+      x = cadd(E, cmul(tw2[k], O));
+    }
+    dst[k] = x;
+  }
+}
+
+template <int G>
+__device__ void tier_fin_a(const KArgs& A, const Item& it, float2* lds) {
+  const DevTier& T = A.tier[it.tier];
+  const int tid = threadIdx.x, P = T.P;
+  const int lg1 = T.lg1, N1 = 1 << lg1, lg2 = T.logP - lg1, N2 = 1 << lg2;
+  const int np = it.w, nc = 2 * np, j = it.k0;
+  const Group grp = A.groups[it.group];
+  const int gsel = it.q, l = grp.l0 + gsel;
+  const int64_t gi = (int64_t)it.tier * A.n_groups_total + it.group;
+  const int s0 = A.tier_slot0[gi], ns = A.tier_nslot[gi];
+  const int64_t stride = (int64_t)G * P;
+  const float2* base = T.partial + (int64_t)s0 * stride + (int64_t)gsel * P;
+  float2* a = lds;
+  float2* b = lds + kTierBuf;
+  float2* twn = lds + 2 * kTierBuf;
+  for (int i = tid; i < N1; i += kThreads) twn[i] = T.tw[i << lg2];  // W_N1^i
+  // the frame's spectrum in the item's columns: its partial slots, summed in
+  // slot order
+  for (int e = tid; e < nc * N1; e += kThreads) {
+    const int c = e & (nc - 1), k1 = e / nc;
+    const int k = (k1 << lg2) + pair_col(j, np, c, N2);
+    float2 acc = make_float2(0.f, 0.f);
+#pragma unroll 8
+    for (int s = 0; s < ns; ++s) acc = cadd(acc, base[s * stride + k]);
+    a[c * N1 + k1] = acc;
+  }
+  __syncthreads();
+  // inverse split (fft_lds.hpp irfft_pre): Z'[k] = E + i O
+  const float2* tw2 = T.tw + P;
+  for (int e = tid; e < nc * N1; e += kThreads) {
+    const int c = e >> lg1, k1 = e & (N1 - 1);
+    const int k2 = pair_col(j, np, c, N2);
+    const int k = (k1 << lg2) + k2;
+    const float2 yk = a[e];
+    float2 z;
+    if (k == 0) {
+      z = make_float2(yk.x + yk.y, yk.x - yk.y);
+    } else {
+      const int pk1 = k2 == 0 ? ((N1 - k1) & (N1 - 1)) : N1 - 1 - k1;
+      const float2 ym = cconj(a[pair_partner(j, np, c) * N1 + pk1]);
+      const float2 E = cadd(yk, ym);
+      const float2 O = cmul(csub(yk, ym), cconj(tw2[k]));
+      z = make_float2(E.x - O.y, E.y + O.x);
+    }
+    b[e] = z;
+  }
+  __syncthreads();
+  const float2* z = fft_stockham<true>(b, a, N1, lg1, twn, nc);
+  float2* dst = T.tinv + (int64_t)l * P;
+  for (int e = tid; e < nc * N1; e += kThreads) {
+    const int c = e & (nc - 1), n1 = e / nc;
+    const int k2 = pair_col(j, np, c, N2);
+    dst[n1 * N2 + k2] = cmul(z[c * N1 + n1], cconj(T.tw[(n1 * k2) & (P - 1)]));
+  }
+}
+
+template <int G>
+__device__ void tier_fin_b(const KArgs& A, const Item& it, float2* lds) {
+  const DevTier& T = A.tier[it.tier];
+  const int tid = threadIdx.x, P = T.P;
+  const int lg1 = T.lg1, lg2 = T.logP - lg1, N2 = 1 << lg2;
+  const int nr = it.w, n10 = it.k0 * nr;
+  const int l = A.groups[it.group].l0 + it.q;
+  float2* a = lds;
+  float2* b = lds + kTierBuf;
+  float2* twn = lds + 2 * kTierBuf;
+  for (int i = tid; i < N2; i += kThreads) twn[i] = T.tw[i << lg1];  // W_N2^i
+  const float2* src = T.tinv + (int64_t)l * P + (int64_t)n10 * N2;
+  for (int e = tid; e < nr * N2; e += kThreads) a[e] = src[e];
+  __syncthreads();
+  const float2* z = fft_stockham<true>(a, b, N2, lg2, twn, nr);
+  // complex samples m = n1 + N1 n2 >= P/2 (n2 >= N2/2): output samples
+  // 2m - P, 2m - P + 1 of the frame
+  const int64_t f = (A.n - it.lag + 1) / T.r - 1;
+  const int64_t y0 = f * (int64_t)P + T.offset;
+  float* ring = T.oring + (int64_t)l * (A.ring_mask + 1);
+  const float scale = 1.0f / (float)(2 * P);
+  const int h2 = N2 >> 1;
+  for (int e = tid; e < nr * h2; e += kThreads) {
+    const int c = e & (nr - 1), h = e / nr;
+    const float2 v = z[c * N2 + h2 + h];
+    const int64_t i0 = 2 * (int64_t)(n10 + c + (h << lg1));
+    ring[(y0 + i0) & A.ring_mask] = v.x * scale;
+    ring[(y0 + i0 + 1) & A.ring_mask] = v.y * scale;
+  }
+}
+
+template <int G>
+__device__ void tier_pass(const KArgs& A, const Item& it, float2* lds) {
+  switch (it.kind) {
+    case K_FFT_A: tier_fft_a<G>(A, it, lds); break;
+    case K_FFT_B: tier_fft_b<G>(A, it, lds); break;
+    case K_FIN_A: tier_fin_a<G>(A, it, lds); break;
+    case K_FIN_B: tier_fin_b<G>(A, it, lds); break;
+    default: break;
+  }
+}
+
 template <typename HT, int G>
 __global__ __launch_bounds__(kThreads) void k_block(const KArgs A) {
   extern __shared__ float2 lds[];
   int b = blockIdx.x;
-  if (A.fc_on) {  // grid: feedback heads | heads | tails | feedback tails
+  if (A.fc_on) {  // grid: feedback heads | heads | transforms | tails | feedback tails
     if (b < A.fc.head_slots) {
       if (b < A.fc.n_heads) fc_head_work<HT, G>(A, b, lds);
       return;
@@ -860,8 +1125,15 @@ __global__ __launch_bounds__(kThreads) void k_block(const KArgs A) {
     }
     return;
   }
+  // later tiers' transform passes of this phase, then the tails
   const int phase = (int)(A.n % A.n_phase);
-  const int i = b - A.head_slots;
+  b -= A.head_slots;
+  if (b < A.tier_slots) {
+    if (b < A.tier_count[phase])
+      tier_pass<G>(A, A.tier_items[(int64_t)phase * A.max_tier_items + b], lds);
+    return;
+  }
+  const int i = b - A.tier_slots;
   if (A.fc_on && i >= A.fc.tail0) {  // feedback terms p >= 2 for c_n
     const int j = i - A.fc.tail0;
     if (j >= A.fc.n_items) return;
@@ -885,81 +1157,6 @@ __global__ __launch_bounds__(kThreads) void k_block(const KArgs A) {
     frame = (A.n - it.lag + 1) / T.r - 1;
   }
   mac_item<HT, G>(A.Q, T, it, A.groups[it.group], frame, lds);
-}
-
-// ---------------------------------------------------------------------------
-// Later tiers (non-uniform partitioning, Sec. III-B): partitions of P_t = r B
-// samples covering filter taps [o_t, o_t + K_t P_t).  Frame f of the tier is
-// input samples [f P_t, (f+1) P_t), complete after block n_f = (f+1) r - 1.
-// Its contribution y[f P_t + o_t + i] (i < P_t) is the second half of the
-// 2 P_t-point inverse FFT of sum_q sum_p H_{t,l,q,p} X_{t,q}(f - p), i.e. the
-// tier's delay o_t is realized in the time domain through the output ring.
-// k_tier runs after k_block on the same stream in the blocks that have
-// tier work: K_FFT items transform frame f into ring slot f mod K_t (in
-// block n_f), K_FINAL items reduce the partial sums that k_block's tail
-// items accumulated over the following blocks, inverse-FFT and store the
-// P_t output samples into the tier's output ring, where the heads of later
-// blocks add them.  LDS: two P_t-bin buffers, the twiddles if they fit, and
-// 256 float2 of reduction scratch.
-// ---------------------------------------------------------------------------
-__host__ __device__ inline int tier_lds(int P) { return 2 * P + tw_lds_len(P) + kThreads; }
-
-template <int G>
-__global__ __launch_bounds__(kThreads) void k_tier(const KArgs A) {
-  extern __shared__ float2 lds[];
-  const int phase = (int)(A.n % A.n_phase);
-  const int i = blockIdx.x;
-  if (i >= A.tier_count[phase]) return;
-  const Item it = A.tier_items[(int64_t)phase * A.max_tier_items + i];
-  if (it.kind != K_FFT && it.kind != K_FINAL) return;
-  const DevTier& T = A.tier[it.tier];
-  const int P = T.P, logP = T.logP;
-  const int tid = threadIdx.x;
-  float2* a = lds;
-  float2* b = lds + P;
-  float2* scratch = lds + 2 * P + tw_lds_len(P);
-  const float2* tw = stage_twiddles(T, lds + 2 * P);
-  const int64_t nf = A.n - it.lag;          // block in which the frame completed
-  const int64_t f = (nf + 1) / T.r - 1;     // the frame
-
-  if (it.kind == K_FFT) {
-    // window: the last 2 P_t input samples up to the end of block nf
-    const float* hq = A.hist + (int64_t)it.q * (A.hist_mask + 1);
-    const int64_t start = (nf + 1) * A.B - 2 * (int64_t)P;
-    for (int m = tid; m < P; m += kThreads)
-      a[m] = make_float2(hq[(start + 2 * m) & A.hist_mask], hq[(start + 2 * m + 1) & A.hist_mask]);
-    __syncthreads();
-    float2* z = fft_stockham<false>(a, b, P, logP, tw);
-    float2* x = (z == a) ? b : a;
-    rfft_post(z, x, P, tw + P);
-    float2* dst = T.X + ((int64_t)it.q * T.K + wrap_slot(f, T.K)) * P;
-    for (int k = tid; k < P; k += kThreads) dst[k] = x[k];
-    return;
-  }
-
-  // K_FINAL: output k0 of its group, frame f
-  const Group grp = A.groups[it.group];
-  const float scale = 1.0f / (float)(2 * P);
-  {
-    const int g = it.k0;
-    const int l = grp.l0 + g;
-    Group tg = grp;  // this tier's partial slots of the group
-    tg.slot0 = A.tier_slot0[(int64_t)it.tier * A.n_groups_total + it.group];
-    tg.nslot = A.tier_nslot[(int64_t)it.tier * A.n_groups_total + it.group];
-    reduce_slots<G>(T, tg, g, a, scratch);
-    irfft_pre(a, b, P, tw + P);
-    float2* z = fft_stockham<true>(b, a, P, logP, tw);
-    float* ring = T.oring + (int64_t)l * (A.ring_mask + 1);
-    const int64_t y0 = f * (int64_t)P + T.offset;  // first output sample of the frame
-    const int half = P >> 1;
-    for (int m = half + tid; m < P; m += kThreads) {
-      const float2 v = z[m];
-      const int64_t i0 = 2 * (int64_t)(m - half);
-      ring[(y0 + i0) & A.ring_mask] = v.x * scale;
-      ring[(y0 + i0 + 1) & A.ring_mask] = v.y * scale;
-    }
-    __syncthreads();
-  }
 }
 
 // Dense copy of partitions 0 and 1 of every pair for the heads:

@@ -95,6 +95,8 @@ struct TierHost {
   float2* partial = nullptr;
   float2* tw = nullptr;
   float* oring = nullptr;
+  float2* tfwd = nullptr;    // tiers >= 1: transform scratch [Q][P] and [L][P]
+  float2* tinv = nullptr;
   int nslots = 0;
   std::vector<int64_t> row;  // host copies
   std::vector<int32_t> kp;
@@ -129,13 +131,12 @@ struct rta_ctx {
   int64_t block = 0;           // index of the next block
 
   void* H01 = nullptr;         // [L][Q][2][P] partitions 0 and 1
-  Item* tier_items = nullptr;  // k_tier lists [n_phase][max_tier_items]
+  Item* tier_items = nullptr;  // later tiers' transform passes [n_phase][max_tier_items]
   int32_t* tier_count = nullptr;
   int32_t* tier_slot0 = nullptr;
   int32_t* tier_nslot = nullptr;
   int max_tier_items = 0;
-  std::vector<int32_t> tier_count_host;  // k_tier items per phase
-  size_t lds_tier = 0;         // k_tier dynamic LDS
+  std::vector<int32_t> tier_count_host;  // transform items per phase
   float* hist = nullptr;
   Item* items = nullptr;
   int32_t* phase_count = nullptr;
@@ -295,15 +296,6 @@ BlockKernel block_kernel(int dtype, int G) {
   return nullptr;
 }
 
-BlockKernel tier_kernel(int G) {
-  switch (G) {
-    case 1: return k_tier<1>;
-    case 2: return k_tier<2>;
-    case 4: return k_tier<4>;
-    default: return nullptr;
-  }
-}
-
 hipError_t launch_spectra(int dtype, dim3 grid, size_t lds, hipStream_t s, const float* taps,
                           const SpecRow* rows, void* H, int P, int logP, const float2* tw,
                           int* range) {
@@ -374,9 +366,10 @@ int validate(double fs, int32_t block, const rta_scheme* scheme, int32_t n_in, i
     if (!is_pow2(size[t]) || size[t] % block != 0 || size[t] > (1 << 13)) return RTA_E_ARG;
     if (t > 0 && size[t] <= size[t - 1]) return RTA_E_ARG;
     if (count[t] < 0 || (count[t] == 0 && t != T - 1)) return RTA_E_ARG;
-    // a later tier's frame needs one block for its FFT and at least one for
-    // its multiply-accumulate before its first output sample is due
-    if (t > 0 && off < (int64_t)size[t] + block) return RTA_E_ARG;
+    // a later tier's frame needs two blocks for its transform, at least one
+    // for its multiply-accumulate and two for its inverse transform before
+    // its first output sample is due (o_t >= P_t + 4B)
+    if (t > 0 && off < (int64_t)size[t] + 4 * (int64_t)block) return RTA_E_ARG;
     off += (int64_t)count[t] * size[t];
   }
   if (count[T - 1] > 0 && max_len > off) return RTA_E_ARG;
@@ -385,18 +378,21 @@ int validate(double fs, int32_t block, const rta_scheme* scheme, int32_t n_in, i
 
 // ---------------------------------------------------------------------------
 // Work lists.  The block index n selects phase n mod n_phase (n_phase =
-// P_max / B).  k_block's list for a phase holds
+// P_max / B).  The tail list of a phase holds
 //   - the first tier's tail items (every phase): partitions p >= 2 of every
 //     (output group, input), cut into chunks of about R rows and bin slices;
 //     each chunk owns one partial slot of its group (the heads do p = 0, 1);
 //   - the multiply-accumulate items of later tiers whose frame is being
 //     accumulated in that block.
-// k_tier's list for a phase holds the later tiers' FFT items (in the block a
-// frame's input completes) and their final items (in the block after the
-// frame's last multiply-accumulate).  Tier t (P_t = r B, offset o_t) gives a
-// frame s = (o_t + B - P_t) / B blocks between input completion and first
-// output; its multiply-accumulate is spread over nmac = min(s, r + 1) - 1
-// blocks (1 with RTA_FLAG_SPIKE).
+// The transform list of a phase holds the later tiers' transform passes
+// (kernels.hpp, "Later tiers"): for a frame whose input completes in block
+// n_f, K_FFT_A in n_f, K_FFT_B in n_f + 1, its multiply-accumulate in
+// n_f + 2 .. n_f + nmac + 1, K_FIN_A in n_f + nmac + 2 and K_FIN_B in
+// n_f + nmac + 3.  Tier t (P_t = r B, offset o_t) leaves s = (o_t + B - P_t)
+// / B blocks between input completion and first output, so nmac <= s - 4;
+// the next frame's K_FFT_B (block n_f + r + 1) overwrites the ring slot that
+// this frame's last partition reads, so nmac <= r - 1.  nmac = min(s - 4,
+// r - 1), or 1 with RTA_FLAG_SPIKE.
 // ---------------------------------------------------------------------------
 struct Bucket {
   int tier, q, p0, k0;
@@ -405,8 +401,8 @@ struct Bucket {
 };
 
 struct Plan {
-  std::vector<std::vector<Item>> block;  // per phase: k_block tail items
-  std::vector<std::vector<Item>> tier;   // per phase: k_tier items
+  std::vector<std::vector<Item>> block;  // per phase: tail items
+  std::vector<std::vector<Item>> tier;   // per phase: transform passes
   std::vector<Group> groups;
   std::vector<int32_t> tier_slot0, tier_nslot;  // [tier][group]
 };
@@ -417,7 +413,7 @@ int tier_nmac(const rta_ctx* c, int t) {
   const int r = T.P / c->B;
   const int64_t s = (T.offset + c->B - T.P) / c->B;
   if (c->flags & RTA_FLAG_SPIKE) return 1;
-  return (int)std::min<int64_t>(s, r + 1) - 1;
+  return (int)std::min<int64_t>(s - 4, r - 1);
 }
 
 // XCD-aware placement: a bucket's items (same tier, input, partitions and
@@ -667,20 +663,33 @@ int build_plan(rta_ctx* c, Plan& plan) {
       plan.tier_nslot[(size_t)t * ngroups + g] = slot - plan.tier_slot0[(size_t)t * ngroups + g];
     }
     T.nslots = slot;
+    // transform passes: items of rows (K_FFT_A, K_FIN_B) and of column
+    // pairs (K_FFT_B, K_FIN_A)
+    const int rpi = tier_rows_per_item(T.logP), ppi = tier_pairs_per_item(T.logP);
+    const int N1 = 1 << tier_lg1(T.logP), N2 = T.P / N1;
+    auto pass = [&](int kind, int ph0, int lag, int q, int g, int nitems, int w) {
+      for (int j = 0; j < nitems; ++j) {
+        Item it{};
+        it.kind = kind;
+        it.tier = t;
+        it.q = q;
+        it.group = g;
+        it.k0 = j;
+        it.w = w;
+        it.lag = lag;
+        plan.tier[(ph0 + lag) % n_phase].push_back(it);
+      }
+    };
     for (int ph0 = r - 1; ph0 < n_phase; ph0 += r) {  // phases in which a frame completes
       for (int q = 0; q < c->Q; ++q) {
         bool used = false;
         for (int l = 0; l < c->L; ++l) used |= T.kp[l * c->Q + q] > 0;
         if (!used) continue;
-        Item it{};
-        it.kind = K_FFT;
-        it.tier = t;
-        it.q = q;
-        it.lag = 0;
-        plan.tier[ph0].push_back(it);
+        pass(K_FFT_A, ph0, 0, q, 0, N1 / rpi, rpi);
+        pass(K_FFT_B, ph0, 1, q, 0, N2 / (2 * ppi), ppi);
       }
       for (size_t i = 0; i < chunks.size(); ++i) {
-        const int lag = 1 + when[i];
+        const int lag = 2 + when[i];
         for (int sl = 0; sl < nslice; ++sl) {
           Item it{};
           it.kind = K_MAC;
@@ -700,14 +709,9 @@ int build_plan(rta_ctx* c, Plan& plan) {
       for (int g = 0; g < ngroups; ++g) {
         if (plan.tier_nslot[(size_t)t * ngroups + g] == 0) continue;
         if (fixed && chunks.empty()) continue;  // no source present
-        for (int gi = 0; gi < plan.groups[g].nl; ++gi) {  // one per output
-          Item it{};
-          it.kind = K_FINAL;
-          it.tier = t;
-          it.group = g;
-          it.k0 = gi;
-          it.lag = nmac;
-          plan.tier[(ph0 + nmac) % n_phase].push_back(it);
+        for (int gi = 0; gi < plan.groups[g].nl; ++gi) {  // every output of the group
+          pass(K_FIN_A, ph0, nmac + 2, gi, g, N2 / (2 * ppi), ppi);
+          pass(K_FIN_B, ph0, nmac + 3, gi, g, N1 / rpi, rpi);
         }
       }
     }
@@ -751,16 +755,35 @@ int build_plan(rta_ctx* c, Plan& plan) {
         const int s0 = plan.tier_slot0[(size_t)it.tier * ngroups + it.group];
         const int ns = plan.tier_nslot[(size_t)it.tier * ngroups + it.group];
         if (it.slot < s0 || it.slot >= s0 + ns) return RTA_E_STATE;
-        if (it.lag < 1 || it.lag > T.P / c->B) return RTA_E_STATE;
+        if (it.lag < 2 || it.lag > tier_nmac(c, it.tier) + 1) return RTA_E_STATE;
       }
     }
     for (const Item& it : plan.tier[ph]) {
       if (it.tier < 1 || it.tier >= c->n_tiers) return RTA_E_STATE;
-      if (it.kind == K_FFT && (it.q < 0 || it.q >= c->Q || it.lag != 0)) return RTA_E_STATE;
-      if (it.kind == K_FINAL && (it.group < 0 || it.group >= ngroups || it.lag < 1 || it.k0 < 0 ||
-                                 it.k0 >= plan.groups[it.group].nl))
+      const TierHost& T = c->tier[it.tier];
+      const int nmac = tier_nmac(c, it.tier);
+      const int N1 = 1 << tier_lg1(T.logP), N2 = T.P / N1;
+      const int rpi = tier_rows_per_item(T.logP), ppi = tier_pairs_per_item(T.logP);
+      const bool rows = it.kind == K_FFT_A || it.kind == K_FIN_B;
+      const int w = rows ? rpi : ppi, n = rows ? N1 / rpi : N2 / (2 * ppi);
+      if (it.w != w || it.k0 < 0 || it.k0 >= n) return RTA_E_STATE;
+      if (rows ? (N1 % rpi != 0 || rpi * N2 > kTierBuf) : (N2 % (2 * ppi) != 0 || 2 * ppi * N1 > kTierBuf))
         return RTA_E_STATE;
-      if (it.kind != K_FFT && it.kind != K_FINAL) return RTA_E_STATE;
+      if (N2 > 128 || N1 > N2) return RTA_E_STATE;
+      switch (it.kind) {
+        case K_FFT_A:
+        case K_FFT_B:
+          if (it.q < 0 || it.q >= c->Q || it.lag != (it.kind == K_FFT_A ? 0 : 1)) return RTA_E_STATE;
+          break;
+        case K_FIN_A:
+        case K_FIN_B:
+          if (it.group < 0 || it.group >= ngroups || it.q < 0 || it.q >= plan.groups[it.group].nl ||
+              it.lag != nmac + (it.kind == K_FIN_A ? 2 : 3))
+            return RTA_E_STATE;
+          break;
+        default:
+          return RTA_E_STATE;
+      }
     }
   }
   return RTA_OK;
@@ -778,6 +801,9 @@ KArgs make_args(const rta_ctx* c, const float* in, float* out, int64_t n) {
     d.partial = T.partial;
     d.tw = T.tw;
     d.oring = T.oring;
+    d.tfwd = T.tfwd;
+    d.tinv = T.tinv;
+    d.lg1 = tier_lg1(T.logP);
     d.offset = T.offset;
     d.P = T.P;
     d.logP = T.logP;
@@ -886,7 +912,7 @@ int64_t drain_end(const rta_ctx* c, int64_t m) {
     const TierHost& T = c->tier[t];
     const int64_t P = T.P, r = T.P / c->B;
     const int64_t fl = floor_div(m * c->B - 1, P) + 1;
-    const int64_t e = t == 0 ? fl + T.K + 1 : (fl + T.K + 1) * r + tier_nmac(c, t);
+    const int64_t e = t == 0 ? fl + T.K + 1 : (fl + T.K + 1) * r + tier_nmac(c, t) + 3;
     end = std::max(end, e + 1);
   }
   return end;
@@ -922,8 +948,8 @@ int serve_boundary(rta_ctx* c, hipStream_t s) {
   return RTA_OK;
 }
 
-// One block: heads of block n and tails of block n + 1 in a single launch,
-// then, in blocks with later-tier FFTs or finals, one k_tier launch.
+// One block: heads of block n, the later tiers' transform passes of this
+// phase and tails of block n + 1 in a single launch.
 // `flag`: raise the host-visible completion flag (rta_process).
 int launch_block(rta_ctx* c, const float* in, float* out, hipStream_t s, bool flag = false) {
   if (c->serve != nullptr) {
@@ -932,14 +958,15 @@ int launch_block(rta_ctx* c, const float* in, float* out, hipStream_t s, bool fl
   }
   KArgs a = make_args(c, in, out, c->block);
   if (flag) a.done_flag = c->m_flag;
-  unsigned grid = (unsigned)(c->head_slots + c->grid_items);
+  const int phase = (int)(c->block % c->n_phase);
+  const int n_tier = c->tier_count_host.empty() ? 0 : c->tier_count_host[phase];
+  a.tier_slots = (n_tier + kXcds - 1) / kXcds * kXcds;  // keeps the tails' XCD residues
+  unsigned grid = (unsigned)(c->head_slots + a.tier_slots + c->grid_items);
   size_t lds = c->lds;
   if (a.fc_on) {
     grid += (unsigned)(a.fc.head_slots + a.fc.n_items);
     lds = c->lds_fused;
   }
-  const int phase = (int)(c->block % c->n_phase);
-  const int n_tier = c->tier_count_host.empty() ? 0 : c->tier_count_host[phase];
   // timing: spans of `timing` consecutive blocks, the first starting at the
   // first block launched after rta_timing_enable; an event before a span's
   // first launch and one after its last
@@ -962,10 +989,6 @@ int launch_block(rta_ctx* c, const float* in, float* out, hipStream_t s, bool fl
   }
   hipLaunchKernelGGL(block_kernel(c->dtype, c->G), dim3(grid), dim3(kThreads), lds, s, a);
   HIP_TRY(c, hipGetLastError());
-  if (n_tier > 0) {
-    hipLaunchKernelGGL(tier_kernel(c->G), dim3(n_tier), dim3(kThreads), c->lds_tier, s, a);
-    HIP_TRY(c, hipGetLastError());
-  }
   if (c->fc != nullptr && c->fc_fused) {
     c->fc->block += 1;  // ran inside this launch
   } else if (c->fc != nullptr) {  // feedback estimate of this block, for the next one
@@ -994,6 +1017,10 @@ int zero_state(rta_ctx* c) {
                               c->stream));
     if (T.oring)
       HIP_TRY(c, hipMemsetAsync(T.oring, 0, sizeof(float) * (size_t)c->L * c->ring_len, c->stream));
+    // the first blocks after a reset run the transform passes of frames
+    // before block 0 (all-zero input): their scratch must hold zeros too
+    if (T.tfwd) HIP_TRY(c, hipMemsetAsync(T.tfwd, 0, sizeof(float2) * (size_t)c->Q * T.P, c->stream));
+    if (T.tinv) HIP_TRY(c, hipMemsetAsync(T.tinv, 0, sizeof(float2) * (size_t)c->L * T.P, c->stream));
   }
   HIP_TRY(c, hipMemsetAsync(c->hist, 0, sizeof(float) * (size_t)c->Q * c->hist_len, c->stream));
   HIP_TRY(c, hipMemsetAsync(c->head_count, 0, sizeof(unsigned int), c->stream));
@@ -1296,8 +1323,12 @@ int create_impl(rta_ctx* c, const std::vector<int>& size, const std::vector<int>
   // block being emitted (their time-domain delay)
   c->ring_len = 1;
   if (c->n_tiers > 1) c->ring_len = int64_t(1) << ilog2(c->tier[c->n_tiers - 1].offset + 2 * c->B);
-  for (int t = 1; t < c->n_tiers; ++t)
-    if ((st = dev_alloc(c, &c->tier[t].oring, (size_t)c->L * c->ring_len)) != RTA_OK) return st;
+  for (int t = 1; t < c->n_tiers; ++t) {
+    TierHost& T = c->tier[t];
+    if ((st = dev_alloc(c, &T.oring, (size_t)c->L * c->ring_len)) != RTA_OK) return st;
+    if ((st = dev_alloc(c, &T.tfwd, (size_t)c->Q * T.P)) != RTA_OK) return st;
+    if ((st = dev_alloc(c, &T.tinv, (size_t)c->L * T.P)) != RTA_OK) return st;
+  }
 
   // spectra, then the heads' dense copy of partitions 0 and 1 (serving: no
   // source yet, so the copy starts as zeros)
@@ -1391,21 +1422,14 @@ int create_impl(rta_ctx* c, const std::vector<int>& size, const std::vector<int>
   const int P0 = c->tier[0].P;
   const int fixed = head_lds(P0, 1, 1).total - 2 * P0;
   c->head_nq = std::max(1, std::min(c->Q, (6144 - fixed) / (2 * P0)));
+  // With later tiers, also a transform pass's buffers (kTierLds).
   c->lds = sizeof(float2) * std::max((size_t)head_lds(P0, 1, c->head_nq).total,
                                      (size_t)kThreads * C * c->G);
+  if (c->n_tiers > 1) c->lds = std::max(c->lds, sizeof(float2) * (size_t)kTierLds);
   if ((int64_t)c->lds + 64 > (int64_t)max_lds) return RTA_E_UNSUPPORTED;
   if (c->lds > 65536)
     HIP_TRY(c, hipFuncSetAttribute(reinterpret_cast<const void*>(block_kernel(c->dtype, c->G)),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds));
-  if (c->n_tiers > 1) {
-    int pmax = 0;
-    for (int t = 1; t < c->n_tiers; ++t) pmax = std::max(pmax, c->tier[t].P);
-    c->lds_tier = sizeof(float2) * (size_t)tier_lds(pmax);
-    if ((int64_t)c->lds_tier + 64 > (int64_t)max_lds) return RTA_E_UNSUPPORTED;
-    if (c->lds_tier > 65536)
-      HIP_TRY(c, hipFuncSetAttribute(reinterpret_cast<const void*>(tier_kernel(c->G)),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_tier));
-  }
   return zero_state(c);
 }
 
@@ -1453,7 +1477,9 @@ std::vector<std::vector<std::pair<int, int>>> scheme_candidates(int B, int64_t m
     int64_t P = B;
     while (true) {
       const int64_t Pn = P * ratio;
-      const int64_t on = 2 * Pn - B;  // start of the next tier
+      // start of the next tier: 2 P - B gives it P / B blocks of slack; at
+      // least P + 4 B
+      const int64_t on = std::max<int64_t>(2 * Pn - B, Pn + 4 * (int64_t)B);
       if (Pn > 8192 || max_len <= on) break;
       sch.push_back({(int)P, (int)((on - o) / P)});
       o = on;

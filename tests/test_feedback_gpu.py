@@ -24,7 +24,7 @@ def weak(filters, scale):
     return [[None if f is None else (f * scale).astype(np.float32) for f in row] for row in filters]
 
 
-@pytest.mark.parametrize("B,scheme", [(32, None), (64, None), (32, [(32, 9), (256, 0)])])
+@pytest.mark.parametrize("B,scheme", [(32, None), (64, None), (32, [(32, 12), (256, 0)])])
 def test_feedback_loop_matches_oracle(rta, B, scheme):
     P, L = 2, 3
     h = make_filters(40, [[3000, 1200, 0], [800, 2600, 300]])
@@ -113,7 +113,7 @@ def test_fused_feedback_with_many_microphones_and_long_paths(rta):
     h = make_filters(54, hl)
     f = weak(make_filters(55, fl), 0.005)
     m = workloads.white_noise(56, 16, 40 * B)
-    with rta.Convolver(h, B, scheme=[(64, 9), (512, 0)]) as cv:
+    with rta.Convolver(h, B, scheme=[(64, 12), (512, 0)]) as cv:
         cv.set_feedback(f)
         y = cv.run(m)
         cv.reset()

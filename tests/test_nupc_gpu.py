@@ -32,14 +32,16 @@ def offsets(scheme):
 
 # (B, scheme, lens[q][l], streamed blocks, flags)
 SCHEMES = [
-    # spread: tier 1 s = 4 of r = 4, tier 2 s = 4 of r = 16
-    (16, [(16, 7), (64, 3), (256, 0)], [[3000, 700, 113]], 40, 0),
-    # a later tier with more slack than one frame: spread capped at r + 1
+    # spread: tier 1 s = 7, r = 4 (3 blocks of multiply-accumulate), tier 2
+    # s = 11, r = 16 (7 blocks)
+    (16, [(16, 10), (64, 4), (256, 0)], [[3000, 700, 161]], 40, 0),
+    # a later tier with more slack than one frame: spread capped at r - 1
     (16, [(16, 20), (64, 0)], [[2500, 321, 319]], 30, 0),
-    # spike: each later-tier frame accumulated in a single block
-    (16, [(16, 7), (64, 3), (256, 0)], [[3000, 300]], 40, "spike"),
+    # spike: each later-tier frame accumulated in a single block; both later
+    # tiers at the least slack allowed (s = 5)
+    (16, [(16, 8), (64, 3), (256, 0)], [[3000, 300]], 40, "spike"),
     # ragged MIMO: pairs ending in every tier, absent pairs, Q != L
-    (32, [(32, 6), (128, 4), (512, 0)], [[4000, 0, 200], [150, 2500, 0]], 40, 0),
+    (32, [(32, 8), (128, 4), (512, 0)], [[4000, 0, 300], [150, 2500, 0]], 40, 0),
     # the standard scheme of block 128 (tiers 128 / 1024 / 8192)
     (128, [(128, 15), (1024, 14), (8192, 0)], [[20000, 17000]], 60, 0),
 ]
@@ -76,7 +78,7 @@ def test_nupc_device_path_equals_host_path(rta):
 
 def test_delta_filters_around_tier_boundaries(rta):
     B = 16
-    scheme = [(16, 7), (64, 3), (256, 0)]
+    scheme = [(16, 8), (64, 3), (256, 0)]
     o1, o2 = offsets(scheme)[1:]
     delays = [o1 - 1, o1, o1 + 1, o1 + 63, o1 + 64, o2 - 1, o2, o2 + 1, o2 + 2 * 256 + 5]
     filt = [[np.eye(1, d + 1, d, dtype=np.float32)[0] for d in delays]]
@@ -96,7 +98,7 @@ def test_scheme_invariance_uniform_vs_nonuniform(rta):
     x = padded_signal(304, 1, 30, B, 6000)
     with rta.Convolver(filt, B) as cv:
         yu = cv.run(x)
-    with rta.Convolver(filt, B, scheme=[(32, 9), (256, 0)]) as cv:
+    with rta.Convolver(filt, B, scheme=[(32, 12), (256, 0)]) as cv:
         yn = cv.run(x)
     err = oracle.error_db(yn, yu)
     say(f"  uniform vs non-uniform: {err.max():.1f} dB")

@@ -89,8 +89,8 @@ LENS = {"A": [1500, 300, 0, 2000], "B": [900, 2000, 1200, 64],
         "C": [2000, 2000, 2000, 2000], "D": [100, 1700, 33, 700]}
 
 
-@pytest.mark.parametrize("B,scheme", [(32, None), (32, [(32, 9), (256, 0)]),
-                                      (16, [(16, 7), (64, 3), (256, 0)])])
+@pytest.mark.parametrize("B,scheme", [(32, None), (32, [(32, 12), (256, 0)]),
+                                      (16, [(16, 8), (64, 3), (256, 0)])])
 def test_admit_release_and_slot_reuse_match_oracle(rta, B, scheme):
     """Three slots: A, B, C fill them; D is refused until A, released at block
     10, has drained, then takes A's slot; B and D leave before the end."""
@@ -124,7 +124,7 @@ def test_mix_equals_sum_of_alone_runs(rta):
               90: [("release", "B")]}
     outs = []
     for ev in (ev_a, ev_b, mix_ev):
-        with rta.Server(2, L, 2000, B, scheme=[(32, 9), (256, 0)]) as srv:
+        with rta.Server(2, L, 2000, B, scheme=[(32, 12), (256, 0)]) as srv:
             outs.append(run_scenario(rta, srv, src, ev, n_blocks)[0])
     err = oracle.error_db(outs[2], outs[0].astype(np.float64) + outs[1])
     say(f"  mix vs sum of alone runs: {err.max():.1f} dB")
@@ -239,7 +239,7 @@ def weak(filters, scale):
 
 @pytest.mark.parametrize("B,scheme,spectra,limit", [
     (32, None, "fp32", FP32_DB),
-    (16, [(16, 7), (64, 3), (256, 0)], "fp32", FP32_DB),
+    (16, [(16, 8), (64, 3), (256, 0)], "fp32", FP32_DB),
     (32, None, "fp16", FP16_DB)])
 def test_serving_with_feedback_cancellation_matches_oracle(rta, B, scheme, spectra, limit):
     """Feedback paths fixed per slot (microphone) on a serving context: sources

@@ -23,7 +23,7 @@ def rta():
     return mod
 
 
-@pytest.mark.parametrize("B,scheme", [(32, None), (16, [(16, 7), (64, 3), (256, 0)])])
+@pytest.mark.parametrize("B,scheme", [(32, None), (16, [(16, 8), (64, 3), (256, 0)])])
 def test_noalloc_admission_matches_the_allocating_one(rta, B, scheme):
     L, max_taps, n_slots, n_blocks = 4, 3000, 2, 120
     N = n_blocks * B
