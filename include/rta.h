@@ -269,9 +269,9 @@ int rta_reset(rta_ctx* ctx);
 int rta_query(rta_ctx* ctx, rta_info* info);
 
 /* Block timing (profiling aid).  Each block is one kernel launch (the heads
- * of this block and the multiply-accumulate of partitions >= 2 for the next
- * one; with later tiers or an unfused feedback convolution, a second and
- * third launch).  After rta_timing_enable(ctx, every) with every >= 1, the
+ * of this block, the later tiers' transform passes and the
+ * multiply-accumulate of partitions >= 2 for the next block; with an
+ * unfused feedback convolution, a second launch).  After rta_timing_enable(ctx, every) with every >= 1, the
  * blocks launched by rta_process() or rta_process_device() are timed in spans
  * of `every` consecutive blocks, the first span starting at the first block
  * launched after the call: one HIP event on the launch stream before a span's
