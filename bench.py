@@ -394,6 +394,36 @@ def sweeps(args, torch, rta, workloads) -> dict:
             "defaults": "1 input -> 32 outputs, 10 s filters, B = 128"}
 
 
+def graph_leg(args, torch, cv, info, xb, yb, direct_ms_per_step):
+    """The same device-resident blocks through rta_graph_launch: runs of M
+    block launches captured once (block index from the device counter),
+    replayed back to back; compared with one rta_process_device call per
+    block."""
+    nph = info["n_phases"]
+    M = -(-max(args.graph_blocks, nph) // nph) * nph
+    M = min(M, xb.shape[0] // nph * nph)
+    reps = max(1, args.steps // M)
+    with cv.graph(xb[:M], yb[:M], M) as g:
+        for _ in range(2):
+            g.launch()
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record()
+        for _ in range(reps):
+            g.launch()
+        ev1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    us = 1e6 * wall / (reps * M)
+    log(f"graph replay: {reps} x {M} blocks: {us:.2f} us/block "
+        f"(direct launches {1e3 * direct_ms_per_step:.2f} us/block)")
+    return {"blocks_per_graph": M, "replays": reps, "us_per_block_wall": us,
+            "us_per_block_events": 1e3 * ev0.elapsed_time(ev1) / (reps * M),
+            "direct_us_per_block_wall": 1e3 * direct_ms_per_step,
+            "mode": "hipGraph of M block launches (device block counter), replayed back to back"}
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -413,12 +443,17 @@ def main(argv=None) -> int:
     ap.add_argument("--copy-probe-mb", type=int, default=0)
     ap.add_argument("--autotune", action="store_true",
                     help="run the library's autotuner first and use its scheme and tiling")
+    ap.add_argument("--tune-cache", default=None,
+                    help="with --autotune: JSON-lines tuning cache file (rta_autotune_cached)")
     ap.add_argument("--timing-every", type=int, default=16,
                     help="time spans of this many consecutive blocks with two HIP events each "
                          "(event packets on every block would slow the stream down)")
     ap.add_argument("--tile", default=None,
                     help="explicit tiling G:items:slices (outputs per group, first-tier items, "
                          "bin slices per row); 0 keeps a default")
+    ap.add_argument("--graph-blocks", type=int, default=64,
+                    help="also time graph replay of runs of this many block launches "
+                         "(rounded up to the work-list period); 0 skips it")
     ap.add_argument("--sweep", default=None,
                     help="comma list of block,length,outputs,feedback or 'all': the paper's sweeps")
     ap.add_argument("--serve", action="store_true",
@@ -475,12 +510,17 @@ def main(argv=None) -> int:
         tuning = rta.make_tuning(outputs_per_group=g_, tail_items=it_, bin_slices=sl_)
     if args.autotune:
         t0 = time.perf_counter()
-        tuning, chosen, us = rta.rta_autotune(fs, B, scheme, Q, L, filt, spectra=args.spectra,
-                                              blocks=64)
+        hit = False
+        if args.tune_cache:
+            tuning, chosen, us, hit = rta.rta_autotune_cached(
+                args.tune_cache, fs, B, scheme, Q, L, filt, spectra=args.spectra, blocks=64)
+        else:
+            tuning, chosen, us = rta.rta_autotune(fs, B, scheme, Q, L, filt,
+                                                  spectra=args.spectra, blocks=64)
         scheme = None if len(chosen) == 1 else chosen
         tuned = {"scheme": chosen, "outputs_per_group": tuning.outputs_per_group,
-                 "tail_items": tuning.tail_items, "us_per_block": us,
-                 "seconds": time.perf_counter() - t0}
+                 "tail_items": tuning.tail_items, "bin_slices": tuning.bin_slices,
+                 "us_per_block": us, "from_cache": hit, "seconds": time.perf_counter() - t0}
         log(f"autotune: {tuned}")
     t0 = time.perf_counter()
     cv = rta.Convolver(filt, B, fs=fs, spectra=args.spectra, scheme=scheme, tuning=tuning)
@@ -529,6 +569,7 @@ def main(argv=None) -> int:
     value = audio_per_step / (ms_per_step / 1e3)
     log(f"timed {args.steps} steps: {ms_per_step * 1e3:.1f} us/step; {kern_us:.1f} us per block "
         f"in event-timed spans of {every} ({n_timed} blocks)")
+    graph = graph_leg(args, torch, cv, info, xb, yb, ms_per_step) if args.graph_blocks else None
     probes = read_probes(torch, rta, int(info["spectra_bytes"]), info["grid"], stream)
 
     # synchronous host-memory blocks: per-block latency including PCIe (after
@@ -645,6 +686,7 @@ def main(argv=None) -> int:
             "kernel_us_timing": timing_how,
         },
         "read_probe": probes,
+        "graph": graph,
         "autotune": tuned,
         "cpu_baseline": cpu,
     }

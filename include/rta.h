@@ -187,6 +187,21 @@ int rta_autotune(double fs, int32_t block, const rta_scheme* scheme,
                  const int64_t* lengths, int32_t spectra, uint32_t flags,
                  int32_t blocks, rta_tuning* best, double* best_us);
 
+/* rta_autotune() behind a tuning cache at `cache_path`, a text file of one
+ * JSON object per line.  The key covers the device (architecture name and
+ * compute-unit count), fs, block, n_in, n_out, a hash of the filter lengths
+ * (not the taps), spectra, flags, blocks and the scheme (or "auto" for
+ * NULL).  On a hit with a valid entry, *best / *best_us come from the file
+ * (*from_cache = 1; no device work); otherwise rta_autotune() runs and one
+ * line is appended (*from_cache = 0).  from_cache may be NULL.  RTA_E_ARG if
+ * the file cannot be appended to (the tuning is still returned).  One
+ * writer per file at a time. */
+int rta_autotune_cached(const char* cache_path, double fs, int32_t block,
+                        const rta_scheme* scheme, int32_t n_in, int32_t n_out,
+                        const float* const* filters, const int64_t* lengths, int32_t spectra,
+                        uint32_t flags, int32_t blocks, rta_tuning* best, double* best_us,
+                        int32_t* from_cache);
+
 /* Process one block, host memory in and out, synchronously.
  *   in   [n_in][block] FP32 host array (row-major), read during the call.
  *   out  [n_out][block] FP32 host array, valid on return.
@@ -207,9 +222,45 @@ int rta_process(rta_ctx* ctx, const float* in, float* out);
  * Enqueues the block's kernel and returns without waiting; d_out is valid
  * once the stream has passed it.  Successive calls must be ordered on one
  * stream: the block index is kept on the host and passed to each launch, so
- * a launch captured into a graph and replayed would repeat the same block. */
+ * a launch captured into a graph and replayed would repeat the same block
+ * (rta_graph_create below captures launches that read a device counter
+ * instead). */
 int rta_process_device(rta_ctx* ctx, const float* d_in, float* d_out,
                        void* stream);
+
+/* Graph replay of runs of blocks (Sec. IV's per-block steps, device memory,
+ * stream-ordered): the per-block launches of n_blocks consecutive blocks
+ * captured once into a hipGraph and replayed, for callers that process
+ * blocks in batches (offline rendering, throughput runs) and want to pay
+ * one graph launch instead of n_blocks kernel launches.
+ *   rta_graph_create: captures launch j (0 <= j < n_blocks) to read
+ *     d_in + j*n_in*block ([n_blocks][n_in][block] FP32, device) and write
+ *     d_out + j*n_out*block ([n_blocks][n_out][block]); the buffers must
+ *     outlive the graph.  The kernels take their block index from a device
+ *     counter (plus j) that the graph's last node advances by n_blocks, so
+ *     replays need no host arguments.  n_blocks must be a multiple of
+ *     rta_info.n_phases (the work lists repeat with that period; 1 for
+ *     uniform partitions).  Allocates the 8-byte counter on first use and
+ *     captures on a private stream; nothing runs on the device.
+ *   rta_graph_launch: processes the context's next n_blocks blocks from the
+ *     current contents of d_in into d_out, stream-ordered on `stream`
+ *     (NULL: the null stream), exactly as n_blocks rta_process_device()
+ *     calls would (bit-identical output).  Mixing with rta_process[_device]
+ *     is allowed as long as the context's block index is a multiple of
+ *     n_phases away from where the graph was captured (RTA_E_STATE
+ *     otherwise); if other launches moved the index since the last replay, a
+ *     one-thread kernel first sets the counter.  Block-timing spans do not
+ *     see replays.
+ *   rta_graph_destroy: NULL-safe; destroy graphs before their context.
+ * RTA_E_UNSUPPORTED for serving contexts and for a feedback convolution in a
+ * separate launch; rta_set_feedback after capture makes rta_graph_launch
+ * return RTA_E_STATE.  RTA_E_DEVICE if capture or instantiation fails (the
+ * context stays usable). */
+typedef struct rta_graph rta_graph;
+int rta_graph_create(rta_ctx* ctx, const float* d_in, float* d_out, int32_t n_blocks,
+                     rta_graph** graph);
+int rta_graph_launch(rta_graph* graph, void* stream);
+int rta_graph_destroy(rta_graph* graph);
 
 /* Feedback cancellation (Sec. III-A Eq. 3, Sec. V).  fb[q*n_out + l] points
  * to lengths[q*n_out + l] FP32 taps of f_ql, the estimated acoustic path

@@ -155,6 +155,8 @@ struct KArgs {
   int32_t pad3;
   int32_t* status;           // host-visible error word: a wait that gave up
                              // stores 1 (system scope); checked by the host
+  const int64_t* n_base;     // graph replay: the block index is *n_base + n
+                             // (null: n itself)
   FcArgs fc;
 };
 
@@ -474,9 +476,9 @@ __device__ void head_reduce(const KArgs& A, const DevTier& T, const Group& grp, 
 // then the workgroup proceeds.  The spin is bounded all the same; a wait that
 // gives up stores 1 in the host-visible error word, which fails the block on
 // the host.
-__device__ void fc_wait(const KArgs& A) {
+__device__ void fc_wait(const KArgs& A, int64_t n) {
   if (threadIdx.x == 0) {
-    const unsigned int target = (unsigned int)((A.n + 1) * A.fc.n_heads) + A.fc.wait_bias;
+    const unsigned int target = (unsigned int)((n + 1) * A.fc.n_heads) + A.fc.wait_bias;
     bool ready = false;
     for (int it = 0; it < A.fc.wait_polls; ++it) {
       if ((int)(__hip_atomic_load(A.fc.done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) - target) >= 0) {
@@ -513,9 +515,8 @@ __host__ __device__ inline HeadLds head_lds(int P, int G, int nq) {
 // of the partial-sum reduction, the critical path under the tails' streaming,
 // independent of G.
 template <typename HT, int G>
-__device__ void head_work(const KArgs& A, const Group& grp, int gsel, float2* lds) {
+__device__ void head_work(const KArgs& A, int64_t n, const Group& grp, int gsel, float2* lds) {
   const int tid = threadIdx.x;
-  const int64_t n = A.n;
   const DevTier& T = A.tier[0];
   const int P = T.P, logP = T.logP;  // P == B
   const HeadLds L = head_lds(P, 1, A.head_nq);
@@ -618,7 +619,7 @@ __device__ void head_work(const KArgs& A, const Group& grp, int gsel, float2* ld
 
   // fused feedback: wait until every feedback head of this launch has
   // published c_{n-1}
-  if (A.fc_on) fc_wait(A);
+  if (A.fc_on) fc_wait(A, n);
 
   // 2. the term p = 0: window -> real FFT -> ring slot n mod K, times H_{l,q,0}
   const int slot0 = wrap_slot(n, T.K);
@@ -789,11 +790,10 @@ __device__ void head_work(const KArgs& A, const Group& grp, int gsel, float2* ld
 // of the 2B samples; then it counts itself done (system scope, after making
 // c visible).  Y' are the synthesis heads' transforms of their outputs.
 template <typename HT, int G>
-__device__ void fc_head_work(const KArgs& A, int j, float2* lds) {
+__device__ void fc_head_work(const KArgs& A, int64_t n, int j, float2* lds) {
   const FcArgs& F = A.fc;
   const DevTier& T = F.T;
   const int P = T.P, logP = T.logP, tid = threadIdx.x;
-  const int64_t n = A.n;
   const Group g0 = F.groups[j / G];
   const int gsel = j - g0.l0;
   float2* Y = lds;
@@ -932,7 +932,7 @@ __device__ __forceinline__ float block_sample(const KArgs& A, int q, int i) {
 }
 
 template <int G>
-__device__ void tier_fft_a(const KArgs& A, const Item& it, float2* lds) {
+__device__ void tier_fft_a(const KArgs& A, int64_t n, const Item& it, float2* lds) {
   const DevTier& T = A.tier[it.tier];
   const int tid = threadIdx.x, P = T.P;
   const int lg1 = T.lg1, N1 = 1 << lg1, lg2 = T.logP - lg1, N2 = 1 << lg2;
@@ -941,11 +941,11 @@ __device__ void tier_fft_a(const KArgs& A, const Item& it, float2* lds) {
   float2* b = lds + kTierBuf;
   float2* twn = lds + 2 * kTierBuf;
   for (int j = tid; j < N2; j += kThreads) twn[j] = T.tw[j << lg1];  // W_N2^j = W_P^{j N1}
-  if (A.fc_on) fc_wait(A);  // the block's samples need c_{n-1}
+  if (A.fc_on) fc_wait(A, n);  // the block's samples need c_{n-1}
   // window: the last 2P samples up to the end of this block (its first
   // 2P - B from the history ring)
   const float* hq = A.hist + (int64_t)q * (A.hist_mask + 1);
-  const int64_t start = (A.n - it.lag + 1) * A.B - 2 * (int64_t)P;
+  const int64_t start = (n - it.lag + 1) * A.B - 2 * (int64_t)P;
   const int cur = 2 * P - A.B;
   auto sample = [&](int i) {
     return i < cur ? hq[(start + i) & A.hist_mask] : block_sample(A, q, i - cur);
@@ -966,7 +966,7 @@ __device__ void tier_fft_a(const KArgs& A, const Item& it, float2* lds) {
 }
 
 template <int G>
-__device__ void tier_fft_b(const KArgs& A, const Item& it, float2* lds) {
+__device__ void tier_fft_b(const KArgs& A, int64_t n, const Item& it, float2* lds) {
   const DevTier& T = A.tier[it.tier];
   const int tid = threadIdx.x, P = T.P;
   const int lg1 = T.lg1, N1 = 1 << lg1, lg2 = T.logP - lg1, N2 = 1 << lg2;
@@ -983,7 +983,7 @@ __device__ void tier_fft_b(const KArgs& A, const Item& it, float2* lds) {
   __syncthreads();
   const float2* Z = fft_stockham<false>(a, b, N1, lg1, twn, nc);
   // packed bins X[k] = E + W_2P^k O from Z[k] and Z[P - k] (fft_lds.hpp)
-  const int64_t f = (A.n - it.lag + 1) / T.r - 1;
+  const int64_t f = (n - it.lag + 1) / T.r - 1;
   float2* dst = T.X + ((int64_t)q * T.K + wrap_slot(f, T.K)) * P;
   const float2* tw2 = T.tw + P;
   for (int e = tid; e < nc * N1; e += kThreads) {
@@ -1007,7 +1007,7 @@ __device__ void tier_fft_b(const KArgs& A, const Item& it, float2* lds) {
 }
 
 template <int G>
-__device__ void tier_fin_a(const KArgs& A, const Item& it, float2* lds) {
+__device__ void tier_fin_a(const KArgs& A, int64_t n, const Item& it, float2* lds) {
   const DevTier& T = A.tier[it.tier];
   const int tid = threadIdx.x, P = T.P;
   const int lg1 = T.lg1, N1 = 1 << lg1, lg2 = T.logP - lg1, N2 = 1 << lg2;
@@ -1063,7 +1063,7 @@ __device__ void tier_fin_a(const KArgs& A, const Item& it, float2* lds) {
 }
 
 template <int G>
-__device__ void tier_fin_b(const KArgs& A, const Item& it, float2* lds) {
+__device__ void tier_fin_b(const KArgs& A, int64_t n, const Item& it, float2* lds) {
   const DevTier& T = A.tier[it.tier];
   const int tid = threadIdx.x, P = T.P;
   const int lg1 = T.lg1, lg2 = T.logP - lg1, N2 = 1 << lg2;
@@ -1079,7 +1079,7 @@ __device__ void tier_fin_b(const KArgs& A, const Item& it, float2* lds) {
   const float2* z = fft_stockham<true>(a, b, N2, lg2, twn, nr);
   // complex samples m = n1 + N1 n2 >= P/2 (n2 >= N2/2): output samples
   // 2m - P, 2m - P + 1 of the frame
-  const int64_t f = (A.n - it.lag + 1) / T.r - 1;
+  const int64_t f = (n - it.lag + 1) / T.r - 1;
   const int64_t y0 = f * (int64_t)P + T.offset;
   float* ring = T.oring + (int64_t)l * (A.ring_mask + 1);
   const float scale = 1.0f / (float)(2 * P);
@@ -1094,12 +1094,12 @@ __device__ void tier_fin_b(const KArgs& A, const Item& it, float2* lds) {
 }
 
 template <int G>
-__device__ void tier_pass(const KArgs& A, const Item& it, float2* lds) {
+__device__ void tier_pass(const KArgs& A, int64_t n, const Item& it, float2* lds) {
   switch (it.kind) {
-    case K_FFT_A: tier_fft_a<G>(A, it, lds); break;
-    case K_FFT_B: tier_fft_b<G>(A, it, lds); break;
-    case K_FIN_A: tier_fin_a<G>(A, it, lds); break;
-    case K_FIN_B: tier_fin_b<G>(A, it, lds); break;
+    case K_FFT_A: tier_fft_a<G>(A, n, it, lds); break;
+    case K_FFT_B: tier_fft_b<G>(A, n, it, lds); break;
+    case K_FIN_A: tier_fin_a<G>(A, n, it, lds); break;
+    case K_FIN_B: tier_fin_b<G>(A, n, it, lds); break;
     default: break;
   }
 }
@@ -1107,10 +1107,13 @@ __device__ void tier_pass(const KArgs& A, const Item& it, float2* lds) {
 template <typename HT, int G>
 __global__ __launch_bounds__(kThreads) void k_block(const KArgs A) {
   extern __shared__ float2 lds[];
+  // the block index: from the launch, or (graph replay) the device counter
+  // plus this launch's place in the graph
+  const int64_t n = A.n_base != nullptr ? *A.n_base + A.n : A.n;
   int b = blockIdx.x;
   if (A.fc_on) {  // grid: feedback heads | heads | transforms | tails | feedback tails
     if (b < A.fc.head_slots) {
-      if (b < A.fc.n_heads) fc_head_work<HT, G>(A, b, lds);
+      if (b < A.fc.n_heads) fc_head_work<HT, G>(A, n, b, lds);
       return;
     }
     b -= A.fc.head_slots;
@@ -1121,16 +1124,16 @@ __global__ __launch_bounds__(kThreads) void k_block(const KArgs A) {
       Group hg = g0;
       hg.l0 = b;
       hg.nl = 1;
-      head_work<HT, G>(A, hg, b - g0.l0, lds);
+      head_work<HT, G>(A, n, hg, b - g0.l0, lds);
     }
     return;
   }
   // later tiers' transform passes of this phase, then the tails
-  const int phase = (int)(A.n % A.n_phase);
+  const int phase = (int)(n % A.n_phase);
   b -= A.head_slots;
   if (b < A.tier_slots) {
     if (b < A.tier_count[phase])
-      tier_pass<G>(A, A.tier_items[(int64_t)phase * A.max_tier_items + b], lds);
+      tier_pass<G>(A, n, A.tier_items[(int64_t)phase * A.max_tier_items + b], lds);
     return;
   }
   const int i = b - A.tier_slots;
@@ -1140,8 +1143,8 @@ __global__ __launch_bounds__(kThreads) void k_block(const KArgs A) {
     const Item it = A.fc.items[j];
     if (it.kind == K_NOP) return;
     DevTier T = A.fc.T;
-    T.partial += (A.n & 1) * (int64_t)T.nslots * G * T.P;
-    mac_item<HT, G>(A.fc.Qf, T, it, A.fc.groups[it.group], A.n, lds);
+    T.partial += (n & 1) * (int64_t)T.nslots * G * T.P;
+    mac_item<HT, G>(A.fc.Qf, T, it, A.fc.groups[it.group], n, lds);
     return;
   }
   if (i >= A.phase_count[phase]) return;
@@ -1150,13 +1153,19 @@ __global__ __launch_bounds__(kThreads) void k_block(const KArgs A) {
   DevTier T = A.tier[it.tier];
   int64_t frame;
   if (it.tier == 0) {
-    frame = A.n + 1;  // first-tier tails prepare the next block
+    frame = n + 1;  // first-tier tails prepare the next block
     T.partial += (frame & 1) * (int64_t)T.nslots * G * T.P;
   } else {
     // later tier: the frame whose input completed in block n - lag
-    frame = (A.n - it.lag + 1) / T.r - 1;
+    frame = (n - it.lag + 1) / T.r - 1;
   }
   mac_item<HT, G>(A.Q, T, it, A.groups[it.group], frame, lds);
+}
+
+// Graph replay's device block counter: set to v (add = 0), or advanced by v
+// (add = 1) by the graph's last node.
+__global__ void k_counter(int64_t* ctr, int64_t v, int32_t add) {
+  if (threadIdx.x == 0) *ctr = add ? *ctr + v : v;
 }
 
 // Dense copy of partitions 0 and 1 of every pair for the heads:

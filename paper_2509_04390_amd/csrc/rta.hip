@@ -142,6 +142,9 @@ struct rta_ctx {
   int32_t* phase_count = nullptr;
   Group* groups = nullptr;
   unsigned int* head_count = nullptr;
+  int64_t* n_dev = nullptr;    // graph replay: device block counter
+  int64_t n_dev_value = -1;    // what it holds once enqueued work is done (-1: unknown)
+  int64_t config_gen = 0;      // bumped when the launch configuration changes
 
   float* h_in = nullptr;       // pinned host staging, mapped into the device
   float* h_out = nullptr;
@@ -948,6 +951,20 @@ int serve_boundary(rta_ctx* c, hipStream_t s) {
   return RTA_OK;
 }
 
+// Grid and dynamic LDS of the launch of block n (its phase's transform
+// passes); sets a.tier_slots.
+void block_geometry(const rta_ctx* c, int64_t n, KArgs& a, unsigned& grid, size_t& lds) {
+  const int phase = (int)(n % c->n_phase);
+  const int n_tier = c->tier_count_host.empty() ? 0 : c->tier_count_host[phase];
+  a.tier_slots = (n_tier + kXcds - 1) / kXcds * kXcds;  // keeps the tails' XCD residues
+  grid = (unsigned)(c->head_slots + a.tier_slots + c->grid_items);
+  lds = c->lds;
+  if (a.fc_on) {
+    grid += (unsigned)(a.fc.head_slots + a.fc.n_items);
+    lds = c->lds_fused;
+  }
+}
+
 // One block: heads of block n, the later tiers' transform passes of this
 // phase and tails of block n + 1 in a single launch.
 // `flag`: raise the host-visible completion flag (rta_process).
@@ -958,15 +975,9 @@ int launch_block(rta_ctx* c, const float* in, float* out, hipStream_t s, bool fl
   }
   KArgs a = make_args(c, in, out, c->block);
   if (flag) a.done_flag = c->m_flag;
-  const int phase = (int)(c->block % c->n_phase);
-  const int n_tier = c->tier_count_host.empty() ? 0 : c->tier_count_host[phase];
-  a.tier_slots = (n_tier + kXcds - 1) / kXcds * kXcds;  // keeps the tails' XCD residues
-  unsigned grid = (unsigned)(c->head_slots + a.tier_slots + c->grid_items);
-  size_t lds = c->lds;
-  if (a.fc_on) {
-    grid += (unsigned)(a.fc.head_slots + a.fc.n_items);
-    lds = c->lds_fused;
-  }
+  unsigned grid = 0;
+  size_t lds = 0;
+  block_geometry(c, c->block, a, grid, lds);
   // timing: spans of `timing` consecutive blocks, the first starting at the
   // first block launched after rta_timing_enable; an event before a span's
   // first launch and one after its last
@@ -1454,6 +1465,8 @@ void free_all(rta_ctx* c) {
   }
   for (void* p : c->dev_allocs) (void)hipFree(p);
   c->dev_allocs.clear();
+  c->n_dev = nullptr;
+  c->n_dev_value = -1;
   if (c->h_in) (void)hipHostFree(c->h_in);
   if (c->h_out) (void)hipHostFree(c->h_out);
   if (c->h_flag) (void)hipHostFree(c->h_flag);
@@ -1855,6 +1868,121 @@ int create_ctx(rta_ctx** out, double fs, int32_t block, const std::vector<int>& 
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Tuning cache: one JSON object per line, keyed by everything the autotuner's
+// choice depends on (device, rate, block, shape, filter lengths, spectra
+// type, flags, scheme or "auto", trial length); filter values do not enter.
+// ---------------------------------------------------------------------------
+std::string tuning_key(double fs, int32_t block, const rta_scheme* scheme, int32_t n_in,
+                       int32_t n_out, const int64_t* lengths, int32_t spectra, uint32_t flags,
+                       int32_t blocks) {
+  int dev = 0;
+  hipDeviceProp_t prop{};
+  std::string arch = "unknown";
+  int cus = 0;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    arch = prop.gcnArchName;
+    cus = prop.multiProcessorCount;
+  }
+  (void)hipGetLastError();
+  uint64_t h = 1469598103934665603ull;  // FNV-1a over the lengths
+  for (int64_t i = 0; i < (int64_t)n_in * n_out; ++i) {
+    uint64_t v = (uint64_t)lengths[i];
+    for (int b = 0; b < 8; ++b) {
+      h ^= (v >> (8 * b)) & 0xffu;
+      h *= 1099511628211ull;
+    }
+  }
+  std::string sch = "auto";
+  if (scheme != nullptr) {
+    sch.clear();
+    for (int t = 0; t < scheme->n_tiers; ++t)
+      sch += (t ? "," : "") + std::to_string(scheme->size[t]) + "x" + std::to_string(scheme->count[t]);
+  }
+  char buf[512];
+  std::snprintf(buf, sizeof buf, "%s;cu=%d;fs=%.17g;B=%d;Q=%d;L=%d;len=%016llx;spectra=%d;flags=%u;blocks=%d;scheme=%s",
+                arch.c_str(), cus, fs, block, n_in, n_out, (unsigned long long)h, spectra, flags,
+                blocks, sch.c_str());
+  // the key sits inside a JSON string: keep it free of quotes and backslashes
+  std::string k = buf;
+  for (char& ch : k)
+    if (ch == '"' || ch == '\\' || (unsigned char)ch < 0x20) ch = '_';
+  return k;
+}
+
+// Parse the integers of `"name": [a, b, ...]` or `"name": a` after `from`.
+bool json_ints(const std::string& line, const char* name, int32_t* v, int n) {
+  const std::string pat = std::string("\"") + name + "\":";
+  const size_t at = line.find(pat);
+  if (at == std::string::npos) return false;
+  const char* p = line.c_str() + at + pat.size();
+  while (*p == ' ') ++p;
+  const bool arr = *p == '[';
+  if (arr) ++p;
+  for (int i = 0; i < n; ++i) {
+    char* end = nullptr;
+    const long x = std::strtol(p, &end, 10);
+    if (end == p) return false;
+    v[i] = (int32_t)x;
+    p = end;
+    while (*p == ' ' || *p == ',') ++p;
+  }
+  return !arr || *p == ']';
+}
+
+bool cache_lookup(const char* path, const std::string& key, rta_tuning* t, double* us) {
+  FILE* fp = std::fopen(path, "r");
+  if (fp == nullptr) return false;
+  const std::string want = "{\"key\": \"" + key + "\",";
+  std::string line;
+  bool found = false;
+  char chunk[1024];
+  while (std::fgets(chunk, sizeof chunk, fp) != nullptr) {
+    line += chunk;
+    if (line.empty() || line.back() != '\n') continue;  // a longer line: keep reading
+    if (line.compare(0, want.size(), want) == 0) {
+      rta_tuning c{};
+      bool ok = json_ints(line, "outputs_per_group", &c.outputs_per_group, 1) &&
+                json_ints(line, "tail_items", &c.tail_items, 1) &&
+                json_ints(line, "tail_rows", &c.tail_rows, 1) &&
+                json_ints(line, "tier_rows", &c.tier_rows, 1) &&
+                json_ints(line, "bin_slices", &c.bin_slices, 1) &&
+                json_ints(line, "n_tiers", &c.n_tiers, 1);
+      ok = ok && c.n_tiers >= 1 && c.n_tiers <= RTA_MAX_TIERS &&
+           json_ints(line, "size", c.size, c.n_tiers) && json_ints(line, "count", c.count, c.n_tiers);
+      const size_t at = line.find("\"us\":");
+      if (ok && at != std::string::npos) {
+        *t = c;  // the last matching line wins
+        *us = std::strtod(line.c_str() + at + 5, nullptr);
+        found = true;
+      }
+    }
+    line.clear();
+  }
+  std::fclose(fp);
+  return found;
+}
+
+int cache_append(const char* path, const std::string& key, const rta_tuning& t, double us) {
+  std::string line = "{\"key\": \"" + key + "\", \"outputs_per_group\": " +
+                     std::to_string(t.outputs_per_group) + ", \"tail_items\": " +
+                     std::to_string(t.tail_items) + ", \"tail_rows\": " + std::to_string(t.tail_rows) +
+                     ", \"tier_rows\": " + std::to_string(t.tier_rows) + ", \"bin_slices\": " +
+                     std::to_string(t.bin_slices) + ", \"n_tiers\": " + std::to_string(t.n_tiers);
+  std::string sz, ct;
+  for (int i = 0; i < t.n_tiers; ++i) {
+    sz += (i ? ", " : "") + std::to_string(t.size[i]);
+    ct += (i ? ", " : "") + std::to_string(t.count[i]);
+  }
+  char usb[64];
+  std::snprintf(usb, sizeof usb, "%.3f", us);
+  line += ", \"size\": [" + sz + "], \"count\": [" + ct + "], \"us\": " + usb + "}\n";
+  FILE* fp = std::fopen(path, "a");
+  if (fp == nullptr) return RTA_E_ARG;
+  const bool ok = std::fputs(line.c_str(), fp) >= 0;
+  return (std::fclose(fp) == 0 && ok) ? RTA_OK : RTA_E_ARG;
+}
+
 extern "C" {
 
 int rta_create_tuned(rta_ctx** out, double fs, int32_t block, const rta_scheme* scheme,
@@ -1916,6 +2044,101 @@ int rta_process_device(rta_ctx* c, const float* d_in, float* d_out, void* stream
   const int st = device_status(c);  // set by a block launched earlier
   if (st != RTA_OK) return st;
   return launch_block(c, d_in, d_out, static_cast<hipStream_t>(stream));
+}
+
+// ---------------------------------------------------------------------------
+// Graph replay: n consecutive block launches captured once into a hipGraph.
+// Each captured launch carries its place j in the run; the kernels take the
+// block index as *n_dev + j, and the graph's last node advances n_dev by n,
+// so every replay processes the next n blocks without re-capture or
+// per-launch arguments from the host.
+// ---------------------------------------------------------------------------
+struct rta_graph {
+  rta_ctx* c = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int32_t n_blocks = 0;
+  int64_t block0 = 0;      // context block index at capture
+  int64_t config_gen = 0;
+};
+
+int rta_graph_create(rta_ctx* c, const float* d_in, float* d_out, int32_t n_blocks,
+                     rta_graph** out) {
+  if (out == nullptr) return RTA_E_ARG;
+  *out = nullptr;
+  if (c == nullptr || d_in == nullptr || d_out == nullptr || n_blocks < 1) return RTA_E_ARG;
+  if (c->poisoned) return RTA_E_DEVICE;
+  if (c->serve != nullptr || (c->fc != nullptr && !c->fc_fused)) return RTA_E_UNSUPPORTED;
+  if (n_blocks % c->n_phase != 0) return RTA_E_ARG;
+  int st = device_status(c);
+  if (st != RTA_OK) return st;
+  if (c->n_dev == nullptr && (st = dev_alloc(c, &c->n_dev, 1)) != RTA_OK) return st;
+  hipStream_t cs = nullptr;
+  HIP_TRY(c, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    for (int32_t j = 0; j < n_blocks && e == hipSuccess; ++j) {
+      KArgs a = make_args(c, d_in + (int64_t)j * c->Q * c->B, d_out + (int64_t)j * c->L * c->B, j);
+      a.n_base = c->n_dev;
+      unsigned grid = 0;
+      size_t lds = 0;
+      block_geometry(c, c->block + j, a, grid, lds);
+      hipLaunchKernelGGL(block_kernel(c->dtype, c->G), dim3(grid), dim3(kThreads), lds, cs, a);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(k_counter, dim3(1), dim3(64), 0, cs, c->n_dev, (int64_t)n_blocks, 1);
+      e = hipGetLastError();
+    }
+    const hipError_t e2 = hipStreamEndCapture(cs, &graph);
+    if (e == hipSuccess) e = e2;
+  }
+  hipGraphExec_t exec = nullptr;
+  if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    return RTA_E_DEVICE;  // capture failed; the context itself is untouched
+  }
+  rta_graph* g = new rta_graph;
+  g->c = c;
+  g->graph = graph;
+  g->exec = exec;
+  g->n_blocks = n_blocks;
+  g->block0 = c->block;
+  g->config_gen = c->config_gen;
+  *out = g;
+  return RTA_OK;
+}
+
+int rta_graph_launch(rta_graph* g, void* stream) {
+  if (g == nullptr) return RTA_E_ARG;
+  rta_ctx* c = g->c;
+  if (c->poisoned) return RTA_E_DEVICE;
+  int st = device_status(c);
+  if (st != RTA_OK) return st;
+  if (g->config_gen != c->config_gen) return RTA_E_STATE;
+  if ((c->block - g->block0) % c->n_phase != 0) return RTA_E_STATE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (c->n_dev_value != c->block) {  // other launches moved the block index
+    hipLaunchKernelGGL(k_counter, dim3(1), dim3(64), 0, s, c->n_dev, c->block, 0);
+    HIP_TRY(c, hipGetLastError());
+  }
+  HIP_TRY(c, hipGraphLaunch(g->exec, s));
+  c->block += g->n_blocks;
+  if (c->fc != nullptr) c->fc->block += g->n_blocks;  // fused: ran inside these launches
+  c->n_dev_value = c->block;
+  return RTA_OK;
+}
+
+int rta_graph_destroy(rta_graph* g) {
+  if (g == nullptr) return RTA_OK;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+  return RTA_OK;
 }
 
 int rta_reset(rta_ctx* c) {
@@ -1985,6 +2208,7 @@ int rta_set_feedback(rta_ctx* c, const float* const* fb, const int64_t* lengths,
     if (st != RTA_OK) return st;
   }
   HIP_TRY(c, hipDeviceSynchronize());
+  c->config_gen += 1;  // graphs captured so far no longer match
   if (c->fc) {
     free_all(c->fc);
     delete c->fc;
@@ -2144,6 +2368,38 @@ int rta_autotune(double fs, int32_t block, const rta_scheme* scheme, int32_t n_i
   *best = bt;
   *best_us = best_t;
   return RTA_OK;
+}
+
+int rta_autotune_cached(const char* cache_path, double fs, int32_t block,
+                        const rta_scheme* scheme, int32_t n_in, int32_t n_out,
+                        const float* const* filters, const int64_t* lengths, int32_t spectra,
+                        uint32_t flags, int32_t blocks, rta_tuning* best, double* best_us,
+                        int32_t* from_cache) {
+  if (cache_path == nullptr || best == nullptr || best_us == nullptr || blocks < 1) return RTA_E_ARG;
+  std::vector<int> size, count;
+  int st = validate(fs, block, scheme, n_in, n_out, filters, lengths, spectra, flags, size, count);
+  if (st != RTA_OK) return st;
+  const std::string key = tuning_key(fs, block, scheme, n_in, n_out, lengths, spectra, flags, blocks);
+  rta_tuning t{};
+  double us = 0;
+  bool hit = cache_lookup(cache_path, key, &t, &us) && tuning_ok(&t);
+  if (hit) {  // the cached scheme must still be a valid one for this shape
+    std::vector<int> csize, ccount;
+    const rta_scheme cs{t.n_tiers, t.size, t.count};
+    hit = validate(fs, block, &cs, n_in, n_out, filters, lengths, spectra, flags, csize, ccount) == RTA_OK;
+  }
+  if (hit) {
+    *best = t;
+    *best_us = us;
+    if (from_cache) *from_cache = 1;
+    return RTA_OK;
+  }
+  st = rta_autotune(fs, block, scheme, n_in, n_out, filters, lengths, spectra, flags, blocks, &t, &us);
+  if (st != RTA_OK) return st;
+  *best = t;
+  *best_us = us;
+  if (from_cache) *from_cache = 0;
+  return cache_append(cache_path, key, t, us);
 }
 
 int rta_serve_create(rta_ctx** out, double fs, int32_t block, const rta_scheme* scheme,

@@ -49,7 +49,8 @@ EXPORTED = ("rta_create", "rta_process", "rta_process_device", "rta_reset",
             "rta_query", "rta_timing_enable", "rta_timing_read", "rta_probe_read",
             "rta_destroy", "rta_strerror", "rta_create_tuned", "rta_autotune",
             "rta_set_feedback", "rta_test_feedback_wait", "rta_serve_create", "rta_serve_admit",
-            "rta_serve_admit_noalloc", "rta_serve_release", "rta_serve_query")
+            "rta_serve_admit_noalloc", "rta_serve_release", "rta_serve_query",
+            "rta_graph_create", "rta_graph_launch", "rta_graph_destroy", "rta_autotune_cached")
 
 
 class rta_scheme(ctypes.Structure):
@@ -128,12 +129,18 @@ _lib.rta_autotune.argtypes = [ctypes.c_double, ctypes.c_int32, ctypes.POINTER(rt
                               ctypes.POINTER(ctypes.c_int64), ctypes.c_int32, ctypes.c_uint32,
                               ctypes.c_int32, ctypes.POINTER(rta_tuning),
                               ctypes.POINTER(ctypes.c_double)]
+_lib.rta_autotune_cached.argtypes = [ctypes.c_char_p] + _lib.rta_autotune.argtypes + [
+    ctypes.POINTER(ctypes.c_int32)]
 _lib.rta_process.argtypes = [ctypes.c_void_p, _fp, _fp]
 _lib.rta_set_feedback.argtypes = [ctypes.c_void_p, ctypes.POINTER(_fp),
                                   ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]
 _lib.rta_test_feedback_wait.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]
 _lib.rta_process_device.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_void_p]
+_lib.rta_graph_create.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                  ctypes.POINTER(ctypes.c_void_p)]
+_lib.rta_graph_launch.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+_lib.rta_graph_destroy.argtypes = [ctypes.c_void_p]
 _lib.rta_reset.argtypes = [ctypes.c_void_p]
 _lib.rta_query.argtypes = [ctypes.c_void_p, ctypes.POINTER(rta_info)]
 _lib.rta_destroy.argtypes = [ctypes.c_void_p]
@@ -264,6 +271,24 @@ def rta_autotune(fs: float, block: int, scheme, n_in: int, n_out: int, filters,
     return best, chosen, us.value
 
 
+def rta_autotune_cached(cache_path: str, fs: float, block: int, scheme, n_in: int, n_out: int,
+                        filters, lengths=None, spectra="fp32", flags: int = 0, blocks: int = 64):
+    """rta_autotune behind a JSON-lines cache file.  Returns (tuning, scheme,
+    mean block time in us, from_cache)."""
+    keep, ptrs, lens, sch = _marshal(filters, n_in, n_out, lengths, scheme)
+    dtype = DTYPES[spectra] if isinstance(spectra, str) else int(spectra)
+    best = rta_tuning()
+    us = ctypes.c_double()
+    hit = ctypes.c_int32()
+    st = _lib.rta_autotune_cached(os.fsencode(cache_path), float(fs), int(block),
+                                  ctypes.byref(sch) if sch is not None else None,
+                                  int(n_in), int(n_out), ptrs, lens, dtype, int(flags), int(blocks),
+                                  ctypes.byref(best), ctypes.byref(us), ctypes.byref(hit))
+    _check(st, "rta_autotune_cached")
+    chosen = [(best.size[t], best.count[t]) for t in range(best.n_tiers)]
+    return best, chosen, us.value, bool(hit.value)
+
+
 def rta_process(ctx, inp: np.ndarray, out: np.ndarray) -> None:
     """inp: [n_in][block] float32 (C-contiguous); out: [n_out][block] float32."""
     assert inp.dtype == np.float32 and inp.flags.c_contiguous
@@ -276,6 +301,22 @@ def rta_process_device(ctx, d_in: int, d_out: int, stream: int = 0) -> None:
     """Device pointers (ints, e.g. torch data_ptr()) and a hipStream_t handle."""
     _check(_lib.rta_process_device(ctx, ctypes.c_void_p(d_in), ctypes.c_void_p(d_out),
                                    ctypes.c_void_p(stream or None)), "rta_process_device")
+
+
+def rta_graph_create(ctx, d_in: int, d_out: int, n_blocks: int):
+    """Device pointers of [n_blocks][n_in][block] and [n_blocks][n_out][block] FP32."""
+    g = ctypes.c_void_p()
+    _check(_lib.rta_graph_create(ctx, ctypes.c_void_p(d_in), ctypes.c_void_p(d_out),
+                                 int(n_blocks), ctypes.byref(g)), "rta_graph_create")
+    return g
+
+
+def rta_graph_launch(graph, stream: int = 0) -> None:
+    _check(_lib.rta_graph_launch(graph, ctypes.c_void_p(stream or None)), "rta_graph_launch")
+
+
+def rta_graph_destroy(graph) -> None:
+    _check(_lib.rta_graph_destroy(graph), "rta_graph_destroy")
 
 
 def rta_set_feedback(ctx, n_in: int, n_out: int, feedback, spectra="fp32") -> None:
@@ -459,6 +500,10 @@ class Convolver:
         assert d_in.numel() == self.n_in * self.block and d_out.numel() == self.n_out * self.block
         rta_process_device(self.ctx, d_in.data_ptr(), d_out.data_ptr(), stream.cuda_stream)
 
+    def graph(self, d_in, d_out, n_blocks: int) -> "Graph":
+        """Capture n_blocks block launches over device tensors (rta_graph_create)."""
+        return Graph(self, d_in, d_out, n_blocks)
+
     def run(self, x: np.ndarray) -> np.ndarray:
         """Stream a whole host signal [n_in][n*block] through rta_process."""
         x = np.asarray(x, np.float32)
@@ -481,6 +526,37 @@ class Convolver:
             self.process_device(xb[b], yb[b])
         torch.cuda.synchronize()
         return yb.permute(1, 0, 2).reshape(self.n_out, nb * self.block).cpu().numpy()
+
+
+class Graph:
+    """A captured run of n_blocks block launches (rta_graph_create) over
+    device tensors d_in [n_blocks][n_in][block] and d_out [n_blocks][n_out][block]."""
+
+    def __init__(self, conv: "Convolver", d_in, d_out, n_blocks: int):
+        import torch
+        assert d_in.is_contiguous() and d_out.is_contiguous()
+        assert d_in.dtype == torch.float32 and d_out.dtype == torch.float32
+        assert d_in.numel() == n_blocks * conv.n_in * conv.block
+        assert d_out.numel() == n_blocks * conv.n_out * conv.block
+        self.conv, self.d_in, self.d_out, self.n_blocks = conv, d_in, d_out, n_blocks
+        self.graph = rta_graph_create(conv.ctx, d_in.data_ptr(), d_out.data_ptr(), n_blocks)
+
+    def launch(self, stream=None) -> None:
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        rta_graph_launch(self.graph, stream.cuda_stream)
+
+    def close(self):
+        if self.graph:
+            rta_graph_destroy(self.graph)
+            self.graph = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 class Server:

@@ -155,3 +155,56 @@ def test_invalid_tuning_is_rejected_before_any_device_call(rta):
         st = rta._lib.rta_create_tuned(ctypes.byref(ctx), 48000.0, 128, None, 1, 1, ptrs, lengths,
                                        0, 0, ctypes.byref(rta.make_tuning(**bad)))
         assert st == rta.RTA_E_ARG and not ctx.value
+
+
+def _fnv1a64(values):
+    h = 1469598103934665603
+    for v in values:
+        for b in int(v).to_bytes(8, "little", signed=True):
+            h ^= b
+            h = (h * 1099511628211) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+def test_tuning_cache_hit_needs_no_device(rta, tmp_path):
+    """A cache line written in the documented format is found by its key and
+    returned without device work (no GPU here: the device part of the key
+    reads 'unknown;cu=0'); a line with an invalid scheme is ignored."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("the key names the visible device; this checks the no-device key")
+    lens = [4000, 2500]
+    filt = [[np.zeros(n, np.float32) for n in lens]]
+    key = (f"unknown;cu=0;fs={format(48000.0, '.17g')};B=64;Q=1;L=2;"
+           f"len={_fnv1a64(lens):016x};spectra=0;flags=0;blocks=8;scheme=auto")
+    path = tmp_path / "tuning.jsonl"
+    path.write_text(
+        '{"key": "other", "outputs_per_group": 4, "tail_items": 0, "tail_rows": 0, '
+        '"tier_rows": 0, "bin_slices": 0, "n_tiers": 1, "size": [64], "count": [0], "us": 1.0}\n'
+        f'{{"key": "{key}", "outputs_per_group": 2, "tail_items": 512, "tail_rows": 0, '
+        '"tier_rows": 0, "bin_slices": 2, "n_tiers": 2, "size": [64, 512], "count": [12, 0], '
+        '"us": 7.25}\n')
+    t, sch, us, hit = rta.rta_autotune_cached(str(path), 48000.0, 64, None, 1, 2, filt, blocks=8)
+    assert hit and sch == [(64, 12), (512, 0)] and us == 7.25
+    assert (t.outputs_per_group, t.tail_items, t.bin_slices) == (2, 512, 2)
+    # a later line for the same key wins, unless its scheme is invalid for this shape
+    with open(path, "a") as fh:
+        fh.write(f'{{"key": "{key}", "outputs_per_group": 1, "tail_items": 0, "tail_rows": 0, '
+                 '"tier_rows": 0, "bin_slices": 0, "n_tiers": 2, "size": [64, 512], '
+                 '"count": [3, 0], "us": 5.0}\n')
+    lib = rta._lib
+    # o_1 = 192 < 512 + 4 * 64: the cached scheme is rejected and the tuner would
+    # run, which needs a device: here that surfaces as an error, not as a hit
+    with pytest.raises(rta.RtaError):
+        rta.rta_autotune_cached(str(path), 48000.0, 64, None, 1, 2, filt, blocks=8)
+    assert lib.rta_autotune_cached(None, 48000.0, 64, None, 1, 2, None, None, 0, 0, 8,
+                                   None, None, None) == rta.RTA_E_ARG
+
+
+def test_graph_entry_points_reject_null_handles(rta):
+    lib = rta._lib
+    assert lib.rta_graph_destroy(None) == 0
+    assert lib.rta_graph_launch(None, None) == rta.RTA_E_ARG
+    g = ctypes.c_void_p()
+    assert lib.rta_graph_create(None, None, None, 8, ctypes.byref(g)) == rta.RTA_E_ARG
+    assert lib.rta_graph_create(None, None, None, 8, None) == rta.RTA_E_ARG
