@@ -449,8 +449,9 @@ def main(argv=None) -> int:
                     help="time spans of this many consecutive blocks with two HIP events each "
                          "(event packets on every block would slow the stream down)")
     ap.add_argument("--tile", default=None,
-                    help="explicit tiling G:items:slices (outputs per group, first-tier items, "
-                         "bin slices per row); 0 keeps a default")
+                    help="explicit tiling G:items:slices[:loads] (outputs per group, first-tier "
+                         "items, bin slices per row, spectra loads 1 non-temporal / 2 ordinary); "
+                         "0 keeps a default")
     ap.add_argument("--graph-blocks", type=int, default=64,
                     help="also time graph replay of runs of this many block launches "
                          "(rounded up to the work-list period); 0 skips it")
@@ -506,8 +507,11 @@ def main(argv=None) -> int:
 
     tuning, tuned = None, None
     if args.tile:
-        g_, it_, sl_ = (int(v) for v in args.tile.split(":"))
-        tuning = rta.make_tuning(outputs_per_group=g_, tail_items=it_, bin_slices=sl_)
+        parts = [int(v) for v in args.tile.split(":")]
+        g_, it_, sl_ = parts[:3]
+        ld_ = parts[3] if len(parts) > 3 else 0
+        tuning = rta.make_tuning(outputs_per_group=g_, tail_items=it_, bin_slices=sl_,
+                                 spectra_loads=ld_)
     if args.autotune:
         t0 = time.perf_counter()
         hit = False
@@ -577,7 +581,7 @@ def main(argv=None) -> int:
     cv.reset()
     lat = []
     out = np.empty((L, B), np.float32)
-    for i in range(16):
+    for i in range(16 if args.latency_blocks or args.paced_blocks else 0):
         rta.rta_process(cv.ctx, np.ascontiguousarray(x[:, i * B:(i + 1) * B]), out)
     cv.reset()
     with no_gc():
@@ -660,19 +664,23 @@ def main(argv=None) -> int:
             "block": B, "n_in": Q, "n_out": L, "taps": n_h, "spectra": args.spectra,
             "tiers": [[int(a_), int(b_)] for a_, b_ in zip(info["tier_size"], info["tier_count"])],
             "phases": info["n_phases"],
+            "tiling": {"outputs_per_group": info["outputs_per_group"], "grid": info["grid"],
+                       "rows_per_item": info["rows_per_item"],
+                       "spectra_loads": "non-temporal" if info["spectra_nontemporal"] else "ordinary"},
         },
         "rtf": (ms_per_step / 1e3) / audio_per_step,
         "channel_filter_seconds_per_s": taps_total / fs * value,
         "deadline_us": deadline,
         "latency": paced,
-        "latency_back_to_back": {"blocks": args.latency_blocks,
-                                 "mode": "back-to-back rta_process, host memory, PCIe included",
-                                 "p50_us": float(np.percentile(lat_us, 50)),
-                                 "p99_us": float(np.percentile(lat_us, 99)),
-                                 "max_us": float(lat_us.max()),
-                                 "max_at_block": int(np.argmax(lat_us)),
-                                 "over_1ms": int(np.sum(lat_us > 1000.0)),
-                                 "xruns": int(np.sum(lat_us > deadline))},
+        "latency_back_to_back": None if not len(lat_us) else {
+            "blocks": args.latency_blocks,
+            "mode": "back-to-back rta_process, host memory, PCIe included",
+            "p50_us": float(np.percentile(lat_us, 50)),
+            "p99_us": float(np.percentile(lat_us, 99)),
+            "max_us": float(lat_us.max()),
+            "max_at_block": int(np.argmax(lat_us)),
+            "over_1ms": int(np.sum(lat_us > 1000.0)),
+            "xruns": int(np.sum(lat_us > deadline))},
         "roofline": {
             "kernel": "k_block",
             "bound": "hbm",

@@ -114,6 +114,8 @@ typedef struct rta_info {
     int32_t poisoned;             /* 1 after RTA_E_DEVICE                  */
     int32_t feedback_paths;       /* 1 while rta_set_feedback paths are set */
     int32_t feedback_fused;       /* 1 if they run inside the block launch  */
+    int32_t spectra_nontemporal;  /* 1 if the spectra are streamed with
+                                     non-temporal loads (rta_tuning)       */
 } rta_info;
 
 /* Create a context.
@@ -141,16 +143,22 @@ int rta_create(rta_ctx** out, double fs, int32_t block,
 /* Tiling of the kernels (performance only: every tiling gives the same
  * output up to FP32 rounding order).  Zero in any field selects the default.
  *   outputs_per_group  G in {1, 2, 4}: outputs sharing one input-spectrum
- *                      load in the multiply-accumulate (default 2 when there
- *                      are at least 16 outputs, else 1).
+ *                      load in the multiply-accumulate (default 4 with later
+ *                      tiers and at least 64 outputs, else 2 with at least
+ *                      16 outputs, else 1).
  *   tail_items         target number of first-tier multiply-accumulate work
- *                      items per block (default 1024).
+ *                      items per block (default 512).
  *   tail_rows          partitions per first-tier item; overrides tail_items.
  *   tier_rows          partitions per later-tier item (default 16).
  *   bin_slices         S in {1, 2, 4, 8}: first-tier items cover 1/S of a
  *                      partition row's bins over S times more rows, so each
  *                      output group owns S times fewer partial sums for the
  *                      output workgroups to reduce (default 1).
+ *   spectra_loads      how the multiply-accumulate streams the spectra:
+ *                      1 = non-temporal loads, 2 = ordinary loads, 0 =
+ *                      default (ordinary for uniform partitions, which
+ *                      re-read every row every block; non-temporal with
+ *                      later tiers and for serving contexts).
  * rta_autotune() also fills the scheme it selected (n_tiers, size, count). */
 typedef struct rta_tuning {
     int32_t outputs_per_group;
@@ -161,6 +169,7 @@ typedef struct rta_tuning {
     int32_t n_tiers;
     int32_t size[RTA_MAX_TIERS];
     int32_t count[RTA_MAX_TIERS];
+    int32_t spectra_loads;
 } rta_tuning;
 
 /* rta_create() with an explicit tiling (NULL: defaults).  The scheme fields
@@ -175,8 +184,9 @@ int rta_create_tuned(rta_ctx** out, double fs, int32_t block,
  * non-uniform schemes with partition ratios 8 (B, 8B, 64B) and 4 (B, 4B,
  * 16B, 64B), each tier starting exactly 2 P_t - B taps into the filter,
  * limited to tiers the longest filter reaches and to sizes <= 8192.  For
- * every candidate scheme and tiling (G in {1, 2, 4} x tail_items in {512,
- * 1024, 2048} x bin_slices in {1, 2, 4}) a context is created, `blocks` blocks of zero input are run
+ * every candidate scheme and tiling (G in {1, 2, 4} x tail_items in {256,
+ * 512, 1024} x bin_slices in {1, 2, 4}, then spectra_loads 1 and 2 for the
+ * best of those) a context is created, `blocks` blocks of zero input are run
  * through rta_process_device() after 16 warm-up blocks, and the mean block
  * time is measured with HIP events.  The fastest is written to *best and its
  * mean block time in microseconds to *best_us.  Takes one to a few seconds

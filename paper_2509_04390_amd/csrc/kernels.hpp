@@ -178,8 +178,10 @@ template <> struct HVec<float2> {
   static constexpr int C = 2;
   static constexpr int U = kUnroll;
   typedef f32x4 raw_t;
+  template <bool NT>
   static __device__ __forceinline__ raw_t load_raw(const float2* p) {
-    return __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p));
+    if (NT) return __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p));
+    return *reinterpret_cast<const f32x4*>(p);
   }
   static __device__ __forceinline__ void unpack(const raw_t& v, float2 (&h)[C]) {
     h[0] = make_float2(v.x, v.y);
@@ -204,8 +206,10 @@ template <> struct HVec<f16c_t> {
   static constexpr int C = 2;
   static constexpr int U = kUnroll16;
   typedef u32x2 raw_t;
+  template <bool NT>
   static __device__ __forceinline__ raw_t load_raw(const f16c_t* p) {
-    return __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(p));
+    if (NT) return __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(p));
+    return *reinterpret_cast<const u32x2*>(p);
   }
   static __device__ __forceinline__ void unpack(const raw_t& v, float2 (&h)[C]) {
     h[0] = f16pair(v.x);
@@ -218,8 +222,10 @@ template <> struct HVec<bf16c_t> {
   static constexpr int C = 2;
   static constexpr int U = kUnroll16;
   typedef u32x2 raw_t;
+  template <bool NT>
   static __device__ __forceinline__ raw_t load_raw(const bf16c_t* p) {
-    return __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(p));
+    if (NT) return __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(p));
+    return *reinterpret_cast<const u32x2*>(p);
   }
   static __device__ __forceinline__ void unpack(const raw_t& v, float2 (&h)[C]) {
     h[0] = bf16pair(v.x);
@@ -238,7 +244,7 @@ __device__ __forceinline__ int wrap_slot(int64_t v, int K) {
 // `frame` is the frame whose delay-line head is slot frame mod K (partition
 // p pairs with slot (frame - p) mod K).
 // ---------------------------------------------------------------------------
-template <typename HT, int G>
+template <typename HT, int G, bool NT>
 __device__ void mac_item(int Qn, const DevTier& T, const Item& it,
                          const Group& grp, int64_t frame, float2* red) {
   constexpr int C = HVec<HT>::C;
@@ -293,7 +299,7 @@ __device__ void mac_item(int Qn, const DevTier& T, const Item& it,
       xr[u] = pu < it.p1 ? *reinterpret_cast<const f32x4*>(Xq + (int64_t)sl * P) : f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int g = 0; g < G; ++g)
-        hr[u][g] = pu < pend[g] ? HVec<HT>::load_raw(hb[g] + (int64_t)pu * P) : raw_t{};
+        hr[u][g] = pu < pend[g] ? HVec<HT>::template load_raw<NT>(hb[g] + (int64_t)pu * P) : raw_t{};
       sl -= step;
       if (sl < 0) sl += K;
     }
@@ -1104,7 +1110,7 @@ __device__ void tier_pass(const KArgs& A, int64_t n, const Item& it, float2* lds
   }
 }
 
-template <typename HT, int G>
+template <typename HT, int G, bool NT>
 __global__ __launch_bounds__(kThreads) void k_block(const KArgs A) {
   extern __shared__ float2 lds[];
   // the block index: from the launch, or (graph replay) the device counter
@@ -1144,7 +1150,7 @@ __global__ __launch_bounds__(kThreads) void k_block(const KArgs A) {
     if (it.kind == K_NOP) return;
     DevTier T = A.fc.T;
     T.partial += (n & 1) * (int64_t)T.nslots * G * T.P;
-    mac_item<HT, G>(A.fc.Qf, T, it, A.fc.groups[it.group], n, lds);
+    mac_item<HT, G, NT>(A.fc.Qf, T, it, A.fc.groups[it.group], n, lds);
     return;
   }
   if (i >= A.phase_count[phase]) return;
@@ -1159,7 +1165,7 @@ __global__ __launch_bounds__(kThreads) void k_block(const KArgs A) {
     // later tier: the frame whose input completed in block n - lag
     frame = (n - it.lag + 1) / T.r - 1;
   }
-  mac_item<HT, G>(A.Q, T, it, A.groups[it.group], frame, lds);
+  mac_item<HT, G, NT>(A.Q, T, it, A.groups[it.group], frame, lds);
 }
 
 // Graph replay's device block counter: set to v (add = 0), or advanced by v

@@ -122,7 +122,9 @@ struct rta_ctx {
   int n_tiers = 0;
   TierHost tier[kMaxTiers];
   int G = 1, rows_per_item = 0, n_phase = 1, max_items = 0, n_items = 0;
-  int tail_items = 1024, tier_rows = 16;
+  int tail_items = 512, tier_rows = 16;
+  int spectra_loads = 0;       // 0 default, 1 non-temporal, 2 ordinary
+  bool nt = true;              // non-temporal spectra loads
   int bin_slices = 1;          // first-tier bin slices per partition row
   int n_groups = 0, head_slots = 0, head_nq = 1;
   int64_t hist_len = 0, ring_len = 0;
@@ -284,13 +286,16 @@ std::vector<float2> twiddles(int P) {
 
 using BlockKernel = void (*)(const KArgs);
 
-BlockKernel block_kernel(int dtype, int G) {
-#define RTA_PICK(HT)                                   \
-  switch (G) {                                         \
-    case 1: return k_block<HT, 1>;                     \
-    case 2: return k_block<HT, 2>;                     \
-    case 4: return k_block<HT, 4>;                     \
-    default: return nullptr;                           \
+// nt: stream the spectra with non-temporal loads (working sets larger than
+// the Infinity Cache) or with ordinary loads (smaller ones, which it can keep
+// between blocks)
+BlockKernel block_kernel(int dtype, int G, bool nt) {
+#define RTA_PICK(HT)                                                   \
+  switch (G) {                                                         \
+    case 1: return nt ? k_block<HT, 1, true> : k_block<HT, 1, false>;  \
+    case 2: return nt ? k_block<HT, 2, true> : k_block<HT, 2, false>;  \
+    case 4: return nt ? k_block<HT, 4, true> : k_block<HT, 4, false>;  \
+    default: return nullptr;                                           \
   }
   if (dtype == RTA_FP32) RTA_PICK(float2)
   if (dtype == RTA_FP16) RTA_PICK(f16c_t)
@@ -998,7 +1003,7 @@ int launch_block(rta_ctx* c, const float* in, float* out, hipStream_t s, bool fl
     a.sub = c->d_c;
     a.out2 = c->d_y;
   }
-  hipLaunchKernelGGL(block_kernel(c->dtype, c->G), dim3(grid), dim3(kThreads), lds, s, a);
+  hipLaunchKernelGGL(block_kernel(c->dtype, c->G, c->nt), dim3(grid), dim3(kThreads), lds, s, a);
   HIP_TRY(c, hipGetLastError());
   if (c->fc != nullptr && c->fc_fused) {
     c->fc->block += 1;  // ran inside this launch
@@ -1430,6 +1435,13 @@ int create_impl(rta_ctx* c, const std::vector<int>& size, const std::vector<int>
   // LDS: the larger of a head's layout (HeadLds) and a tail item's row-group
   // reduction.  head_nq: as many inputs per pass as fit in 48 KB, at least 1.
   const int C = vec_bins(c->dtype);
+  // uniform partitions re-read every spectrum row every block: ordinary
+  // loads stream them faster (measured with 123 MB and 295 MB of FP32
+  // spectra, inside and beyond the Infinity Cache); later tiers touch their
+  // rows once per frame, and serving contexts stream whatever is admitted:
+  // non-temporal loads there
+  c->nt = c->spectra_loads == 1 ||
+          (c->spectra_loads == 0 && (c->serve != nullptr || c->n_tiers > 1));
   const int P0 = c->tier[0].P;
   const int fixed = head_lds(P0, 1, 1).total - 2 * P0;
   c->head_nq = std::max(1, std::min(c->Q, (6144 - fixed) / (2 * P0)));
@@ -1439,7 +1451,7 @@ int create_impl(rta_ctx* c, const std::vector<int>& size, const std::vector<int>
   if (c->n_tiers > 1) c->lds = std::max(c->lds, sizeof(float2) * (size_t)kTierLds);
   if ((int64_t)c->lds + 64 > (int64_t)max_lds) return RTA_E_UNSUPPORTED;
   if (c->lds > 65536)
-    HIP_TRY(c, hipFuncSetAttribute(reinterpret_cast<const void*>(block_kernel(c->dtype, c->G)),
+    HIP_TRY(c, hipFuncSetAttribute(reinterpret_cast<const void*>(block_kernel(c->dtype, c->G, c->nt)),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds));
   return zero_state(c);
 }
@@ -1820,7 +1832,8 @@ bool tuning_ok(const rta_tuning* tuning) {
   const int g = tuning->outputs_per_group;
   const int s = tuning->bin_slices;
   return !((g != 0 && g != 1 && g != 2 && g != 4) || tuning->tail_items < 0 || tuning->tail_rows < 0 ||
-           tuning->tier_rows < 0 || (s != 0 && s != 1 && s != 2 && s != 4 && s != 8));
+           tuning->tier_rows < 0 || (s != 0 && s != 1 && s != 2 && s != 4 && s != 8) ||
+           tuning->spectra_loads < 0 || tuning->spectra_loads > 2);
 }
 
 int create_ctx(rta_ctx** out, double fs, int32_t block, const std::vector<int>& size,
@@ -1837,15 +1850,18 @@ int create_ctx(rta_ctx** out, double fs, int32_t block, const std::vector<int>& 
   c->L = n_out;
   c->dtype = spectra;
   c->flags = flags;
-  // tiling defaults measured on the 1 -> 32 x 480,000-tap workload: two
-  // outputs per workgroup and about 1,024 first-tier items
-  c->G = n_out >= 16 ? 2 : 1;
+  // tiling defaults from sweeps on MI355X (1 -> 32 x 480,000 taps, 1 -> 64 x
+  // 576,000 taps, FP32 and FP16, uniform; 4 -> 64 x U[3,12] s, FP16,
+  // 128/1024/8192): about 512 first-tier items, two outputs per workgroup
+  // from 16 outputs on, four with later tiers and 64 outputs or more
+  c->G = (size.size() > 1 && n_out >= 64) ? 4 : n_out >= 16 ? 2 : 1;
   if (tuning != nullptr) {
     if (tuning->outputs_per_group) c->G = tuning->outputs_per_group;
     if (tuning->tail_items) c->tail_items = tuning->tail_items;
     if (tuning->tail_rows) c->rows_per_item = tuning->tail_rows;
     if (tuning->tier_rows) c->tier_rows = tuning->tier_rows;
     if (tuning->bin_slices) c->bin_slices = tuning->bin_slices;
+    c->spectra_loads = tuning->spectra_loads;
   }
   if (cfg != nullptr) {
     c->serve = new (std::nothrow) Serve();
@@ -1950,6 +1966,7 @@ bool cache_lookup(const char* path, const std::string& key, rta_tuning* t, doubl
                 json_ints(line, "n_tiers", &c.n_tiers, 1);
       ok = ok && c.n_tiers >= 1 && c.n_tiers <= RTA_MAX_TIERS &&
            json_ints(line, "size", c.size, c.n_tiers) && json_ints(line, "count", c.count, c.n_tiers);
+      if (!json_ints(line, "spectra_loads", &c.spectra_loads, 1)) c.spectra_loads = 0;  // optional
       const size_t at = line.find("\"us\":");
       if (ok && at != std::string::npos) {
         *t = c;  // the last matching line wins
@@ -1968,7 +1985,8 @@ int cache_append(const char* path, const std::string& key, const rta_tuning& t, 
                      std::to_string(t.outputs_per_group) + ", \"tail_items\": " +
                      std::to_string(t.tail_items) + ", \"tail_rows\": " + std::to_string(t.tail_rows) +
                      ", \"tier_rows\": " + std::to_string(t.tier_rows) + ", \"bin_slices\": " +
-                     std::to_string(t.bin_slices) + ", \"n_tiers\": " + std::to_string(t.n_tiers);
+                     std::to_string(t.bin_slices) + ", \"spectra_loads\": " +
+                     std::to_string(t.spectra_loads) + ", \"n_tiers\": " + std::to_string(t.n_tiers);
   std::string sz, ct;
   for (int i = 0; i < t.n_tiers; ++i) {
     sz += (i ? ", " : "") + std::to_string(t.size[i]);
@@ -2084,7 +2102,7 @@ int rta_graph_create(rta_ctx* c, const float* d_in, float* d_out, int32_t n_bloc
       unsigned grid = 0;
       size_t lds = 0;
       block_geometry(c, c->block + j, a, grid, lds);
-      hipLaunchKernelGGL(block_kernel(c->dtype, c->G), dim3(grid), dim3(kThreads), lds, cs, a);
+      hipLaunchKernelGGL(block_kernel(c->dtype, c->G, c->nt), dim3(grid), dim3(kThreads), lds, cs, a);
       e = hipGetLastError();
     }
     if (e == hipSuccess) {
@@ -2182,6 +2200,7 @@ int rta_query(rta_ctx* c, rta_info* info) {
   info->poisoned = c->poisoned ? 1 : 0;
   info->feedback_paths = c->fc != nullptr ? 1 : 0;
   info->feedback_fused = c->fc != nullptr && c->fc_fused ? 1 : 0;
+  info->spectra_nontemporal = c->nt ? 1 : 0;
   return c->poisoned ? RTA_E_DEVICE : RTA_OK;
 }
 
@@ -2246,7 +2265,7 @@ int rta_set_feedback(rta_ctx* c, const float* const* fb, const int64_t* lengths,
     c->fc_fused = fc->dtype == c->dtype && fc->G == c->G && fc->n_tiers == 1 && fc->tier[0].K >= 3 &&
                   fc->tier[0].P == P && (int64_t)c->lds_fused + 64 <= (int64_t)max_lds;
     if (c->fc_fused && c->lds_fused > 65536)
-      HIP_TRY(c, hipFuncSetAttribute(reinterpret_cast<const void*>(block_kernel(c->dtype, c->G)),
+      HIP_TRY(c, hipFuncSetAttribute(reinterpret_cast<const void*>(block_kernel(c->dtype, c->G, c->nt)),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_fused));
   }
   // serving: the paths belong to the slots; live sources stay, released ones
@@ -2345,7 +2364,7 @@ int rta_autotune(double fs, int32_t block, const rta_scheme* scheme, int32_t n_i
   rta_tuning bt{};
   for (int g : {1, 2, 4}) {
     if (g > n_out) continue;
-    for (int items : {512, 1024, 2048})
+    for (int items : {256, 512, 1024})
       for (int slices : {1, 2, 4}) {
         rta_tuning tu{};
         tu.outputs_per_group = g;
@@ -2359,6 +2378,18 @@ int rta_autotune(double fs, int32_t block, const rta_scheme* scheme, int32_t n_i
           bt = tu;
         }
       }
+  }
+  // stage 3: how the spectra are streamed, for that tiling
+  for (int loads : {1, 2}) {
+    rta_tuning tu = bt;
+    tu.spectra_loads = loads;
+    double us = 0;
+    const int s2 = trial(schemes[best_s], tu, &us);
+    if (s2 == RTA_E_DEVICE) return s2;
+    if (s2 == RTA_OK && us < best_t) {
+      best_t = us;
+      bt = tu;
+    }
   }
   bt.n_tiers = (int32_t)schemes[best_s].size();
   for (int t = 0; t < bt.n_tiers; ++t) {

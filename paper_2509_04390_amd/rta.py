@@ -81,7 +81,8 @@ class rta_info(ctypes.Structure):
                 ("rows_per_item", ctypes.c_int32),
                 ("poisoned", ctypes.c_int32),
                 ("feedback_paths", ctypes.c_int32),
-                ("feedback_fused", ctypes.c_int32)]
+                ("feedback_fused", ctypes.c_int32),
+                ("spectra_nontemporal", ctypes.c_int32)]
 
 
 class rta_tuning(ctypes.Structure):
@@ -92,7 +93,8 @@ class rta_tuning(ctypes.Structure):
                 ("bin_slices", ctypes.c_int32),
                 ("n_tiers", ctypes.c_int32),
                 ("size", ctypes.c_int32 * RTA_MAX_TIERS),
-                ("count", ctypes.c_int32 * RTA_MAX_TIERS)]
+                ("count", ctypes.c_int32 * RTA_MAX_TIERS),
+                ("spectra_loads", ctypes.c_int32)]
 
 
 class rta_serve_config(ctypes.Structure):
@@ -219,10 +221,11 @@ def _marshal(filters, n_in, n_out, lengths, scheme):
 
 
 def make_tuning(outputs_per_group=0, tail_items=0, tail_rows=0, tier_rows=0,
-                bin_slices=0) -> rta_tuning:
+                bin_slices=0, spectra_loads=0) -> rta_tuning:
     t = rta_tuning()
     t.outputs_per_group, t.tail_items = outputs_per_group, tail_items
     t.tail_rows, t.tier_rows, t.bin_slices = tail_rows, tier_rows, bin_slices
+    t.spectra_loads = spectra_loads
     return t
 
 
