@@ -60,6 +60,18 @@ typedef enum rta_dtype { RTA_FP32 = 0, RTA_FP16 = 1, RTA_BF16 = 2 } rta_dtype;
 #define RTA_FLAG_SPIKE   0x1u  /* NUPC: accumulate each later-tier frame in
                                   the single block after its FFT instead of
                                   spreading it over the frame's slack.     */
+/* The n_f = 3 n_x variant (Sec. V, last paragraph): B-tap partitions with
+ * 3B-point transforms (3B/2 packed bins per spectrum row, 1.5x the bytes of
+ * n_f = 2B), input window [x_{n-2}, x_{n-1}, x_n], output = the last B of
+ * the 3B samples.  Its point is the feedback convolution: the accumulated
+ * spectrum of output l in block n is the transform of a frame whose last 2B
+ * samples are [y_l(n-1), y_l(n)], exactly what B-tap feedback partitions
+ * need, so rta_set_feedback's convolution takes those spectra as they are
+ * instead of transforming y again (n_out fewer transforms per block).
+ * Uniform partitions only (RTA_E_ARG otherwise); not for serving contexts
+ * (RTA_E_UNSUPPORTED); rta_set_feedback then needs the same spectrum type as
+ * the context and runs fused (RTA_E_UNSUPPORTED otherwise). */
+#define RTA_FLAG_NF3     0x2u
 
 /* Partition scheme (Sec. III-B: uniform and non-uniform partitioning).
  *   size[t]  partition length of tier t in samples; size[0] must equal the
@@ -116,6 +128,8 @@ typedef struct rta_info {
     int32_t feedback_fused;       /* 1 if they run inside the block launch  */
     int32_t spectra_nontemporal;  /* 1 if the spectra are streamed with
                                      non-temporal loads (rta_tuning)       */
+    int32_t fft_size;             /* first tier's real transform length:
+                                     2*block, or 3*block with RTA_FLAG_NF3 */
 } rta_info;
 
 /* Create a context.

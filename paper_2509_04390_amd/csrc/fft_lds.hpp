@@ -96,6 +96,86 @@ __device__ float2* fft_stockham(float2* a, float2* b, int N, int logN,
   return a;
 }
 
+// Batched complex FFT of length N = 3 * 2^m (the 3B-point real transforms of
+// the n_f = 3 n_x variant run as N = 3B/2-point complex ones): a radix-3
+// Stockham stage first (sub-transform length 1, no twiddles), then radix-4
+// stages and a last radix-2 stage over the 2^m factor, with the same stage
+// rule as fft_stockham and twiddles W_N^j from `tw` (N entries).  Index
+// arithmetic divides by N / R and takes k = j mod Ns with Ns = 3 * 4^i, so
+// it is kept apart from the power-of-two routine.  Every thread of the
+// workgroup must call it; returns the buffer with the results, ends with a
+// barrier.
+template <bool INV>
+__device__ float2* fft_stockham3(float2* a, float2* b, int N, int m,
+                                 const float2* __restrict__ tw, int nb = 1) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  constexpr float kS3 = 0.86602540378443864676f;  // sqrt(3) / 2
+  {
+    const int third = N / 3;
+    for (int w = tid; w < nb * third; w += nt) {
+      const int bb = w / third, j = w - bb * third;
+      const float2* ab = a + bb * N;
+      float2* bbuf = b + bb * N;
+      const float2 v0 = ab[j], v1 = ab[j + third], v2 = ab[j + 2 * third];
+      const float2 t1 = cadd(v1, v2);
+      const float2 t2 = make_float2(v0.x - 0.5f * t1.x, v0.y - 0.5f * t1.y);
+      const float2 d = csub(v1, v2);
+      // forward: y1 = t2 - i s d, y2 = t2 + i s d (s = sqrt(3)/2); inverse swaps
+      const float2 isd = INV ? make_float2(-kS3 * d.y, kS3 * d.x) : make_float2(kS3 * d.y, -kS3 * d.x);
+      bbuf[3 * j] = cadd(v0, t1);
+      bbuf[3 * j + 1] = cadd(t2, isd);
+      bbuf[3 * j + 2] = csub(t2, isd);
+    }
+    __syncthreads();
+    float2* t = a; a = b; b = t;
+  }
+  int Ns = 3, rem = m;
+  while (rem > 0) {
+    const int R = rem >= 2 ? 4 : 2;
+    const int per = N / R;
+    const int ts = N / (Ns * R);
+    for (int w = tid; w < nb * per; w += nt) {
+      const int bb = w / per, j = w - bb * per;
+      const float2* ab = a + bb * N;
+      float2* bbuf = b + bb * N;
+      const int k = j % Ns;
+      const int base = (j - k) * R + k;
+      if (R == 4) {
+        float2 v0 = ab[j], v1 = ab[j + per], v2 = ab[j + 2 * per], v3 = ab[j + 3 * per];
+        float2 w1 = tw[k * ts], w2 = tw[2 * k * ts], w3 = tw[3 * k * ts];
+        if (INV) { w1.y = -w1.y; w2.y = -w2.y; w3.y = -w3.y; }
+        v1 = cmul(v1, w1); v2 = cmul(v2, w2); v3 = cmul(v3, w3);
+        const float2 s02 = cadd(v0, v2), d02 = csub(v0, v2);
+        const float2 s13 = cadd(v1, v3), d13 = csub(v1, v3);
+        const float2 jd = INV ? make_float2(-d13.y, d13.x) : make_float2(d13.y, -d13.x);
+        bbuf[base] = cadd(s02, s13);
+        bbuf[base + Ns] = cadd(d02, jd);
+        bbuf[base + 2 * Ns] = csub(s02, s13);
+        bbuf[base + 3 * Ns] = csub(d02, jd);
+      } else {
+        float2 v0 = ab[j], v1 = ab[j + per];
+        float2 w1 = tw[k * ts];
+        if (INV) w1.y = -w1.y;
+        v1 = cmul(v1, w1);
+        bbuf[base] = cadd(v0, v1);
+        bbuf[base + Ns] = csub(v0, v1);
+      }
+    }
+    __syncthreads();
+    float2* t = a; a = b; b = t;
+    Ns *= R;
+    rem -= R == 4 ? 2 : 1;
+  }
+  return a;
+}
+
+// Complex FFT of length N = 2^logN (r3 = 0) or N = 3 * 2^logN (r3 = 1).
+template <bool INV>
+__device__ __forceinline__ float2* fft_any(float2* a, float2* b, int N, int logN, int r3,
+                                           const float2* __restrict__ tw, int nb = 1) {
+  return r3 ? fft_stockham3<INV>(a, b, N, logN, tw, nb) : fft_stockham<INV>(a, b, N, logN, tw, nb);
+}
+
 // Packed spectra of nb real signals of 2P samples whose complex FFTs Z
 // (length P each, [nb][P]) are in `Z`; writes [nb][P] packed bins to `X`
 // (must not alias Z).  tw2 = W_2P^k table.  Ends with a barrier.

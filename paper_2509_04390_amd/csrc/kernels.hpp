@@ -96,6 +96,9 @@ struct DevTier {
   int32_t P, logP, K, nslots;
   int32_t r;                 // P / B: blocks per frame
   int32_t lg1;               // tiers >= 1: log2 N1, P = N1 N2, N1 <= N2
+  int32_t r3;                // 1: P = 3 * 2^logP (the n_f = 3 n_x first tier:
+                             // B-tap partitions, 3B-point transforms, 3B/2 bins)
+  int32_t pad5;
 };
 
 // Feedback convolution fused into the synthesis launch (Sec. III-A Eq. 3,
@@ -152,7 +155,8 @@ struct KArgs {
   const int32_t* live;       // [Q] serving: 0 = the slot's input reads as zero
                              // (null: every input is live)
   int32_t fc_on;             // the feedback convolution runs in this launch
-  int32_t pad3;
+  int32_t nf3;               // n_f = 3 n_x: the heads hand their output spectra
+                             // to the feedback convolution (no transform of y)
   int32_t* status;           // host-visible error word: a wait that gave up
                              // stores 1 (system scope); checked by the host
   const int64_t* n_base;     // graph replay: the block index is *n_base + n
@@ -524,7 +528,9 @@ template <typename HT, int G>
 __device__ void head_work(const KArgs& A, int64_t n, const Group& grp, int gsel, float2* lds) {
   const int tid = threadIdx.x;
   const DevTier& T = A.tier[0];
-  const int P = T.P, logP = T.logP;  // P == B
+  // P bins per row, half the window of 2P samples: P = B (n_f = 2B), or
+  // P = 3B/2 (n_f = 3B, T.r3)
+  const int P = T.P, logP = T.logP;
   const HeadLds L = head_lds(P, 1, A.head_nq);
   float2* Y = lds + L.y;
   float2* Xa = lds + L.xa;
@@ -544,8 +550,11 @@ __device__ void head_work(const KArgs& A, int64_t n, const Group& grp, int gsel,
   const int E = grp.nl * P;
   const int nb0 = min(A.head_nq, A.Q);
   const int ept = (E + kThreads - 1) / kThreads;       // output elements per thread
-  const int half = P >> 1;
-  const int eo = grp.nl * half;                         // output sample pairs
+  const int hb = A.B >> 1;                              // sample pairs per output block
+  const int m0 = P - hb;                                // its first complex sample
+  const int eo = grp.nl * hb;                           // output sample pairs
+  const int cur = 2 * P - A.B;                          // window samples from the history
+  const int64_t wh0 = (n + 1) * A.B - 2 * (int64_t)P;   // stream index of window sample 0
   // (fused feedback: the window needs c_{n-1}, which this launch's feedback
   // heads are still computing, so it is not prefetched)
   const bool pre_w = nb0 * P <= WMAX * kThreads && !A.fc_on;
@@ -565,15 +574,15 @@ __device__ void head_work(const KArgs& A, int64_t n, const Group& grp, int gsel,
     const int i0 = 2 * m, i1 = 2 * m + 1;
     float w0, w1;
     if (A.sub == nullptr) {
-      w0 = i0 < P ? hq[((n - 1) * A.B + i0) & A.hist_mask] : iq[i0 - P];
-      w1 = i1 < P ? hq[((n - 1) * A.B + i1) & A.hist_mask] : iq[i1 - P];
+      w0 = i0 < cur ? hq[(wh0 + i0) & A.hist_mask] : iq[i0 - cur];
+      w1 = i1 < cur ? hq[(wh0 + i1) & A.hist_mask] : iq[i1 - cur];
     } else {  // microphone minus the previous block's feedback estimate
-      w0 = i0 < P ? hq[((n - 1) * A.B + i0) & A.hist_mask] : iq[i0 - P] - sub_at(q, i0 - P);
-      w1 = i1 < P ? hq[((n - 1) * A.B + i1) & A.hist_mask] : iq[i1 - P] - sub_at(q, i1 - P);
+      w0 = i0 < cur ? hq[(wh0 + i0) & A.hist_mask] : iq[i0 - cur] - sub_at(q, i0 - cur);
+      w1 = i1 < cur ? hq[(wh0 + i1) & A.hist_mask] : iq[i1 - cur] - sub_at(q, i1 - cur);
     }
     if (A.live != nullptr && A.live[q] == 0) {  // a select, so NaN input stays out
-      if (i0 >= P) w0 = 0.f;
-      if (i1 >= P) w1 = 0.f;
+      if (i0 >= cur) w0 = 0.f;
+      if (i1 >= cur) w1 = 0.f;
     }
     return make_float2(w0, w1);
   };
@@ -605,7 +614,7 @@ __device__ void head_work(const KArgs& A, int64_t n, const Group& grp, int gsel,
 #pragma unroll
       for (int t = 0; t < TMAX; ++t) {
         if (e < eo && t + 1 < A.n_tiers) {
-          const int g = e / half, j = 2 * (e - g * half);
+          const int g = e / hb, j = 2 * (e - g * hb);
           const float* ring = A.tier[t + 1].oring + (int64_t)(grp.l0 + g) * (A.ring_mask + 1);
           rv[i][t][0] = ring[(n * A.B + j) & A.ring_mask];
           rv[i][t][1] = ring[(n * A.B + j + 1) & A.ring_mask];
@@ -641,7 +650,7 @@ __device__ void head_work(const KArgs& A, int64_t n, const Group& grp, int gsel,
       for (int e = tid; e < nb * P; e += kThreads) Xa[e] = window(e, q0);
     }
     __syncthreads();
-    float2* z = fft_stockham<false>(Xa, Xb, P, logP, tw, nb);
+    float2* z = fft_any<false>(Xa, Xb, P, logP, T.r3, tw, nb);
     float2* x = (z == Xa) ? Xb : Xa;
     rfft_post(z, x, P, tw + P, nb);
     if (grp.l0 == 0) {  // the first group stores the block for later launches
@@ -686,16 +695,26 @@ __device__ void head_work(const KArgs& A, int64_t n, const Group& grp, int gsel,
     __syncthreads();
   }
 
+  // n_f = 3B (Sec. V): this output's accumulated spectrum is the spectrum
+  // of a 3B-sample frame whose last 2B samples are [y_l(n-1), y_l(n)], all
+  // the feedback filters' B-tap partitions need, so it goes into slot n of
+  // the feedback delay line as it is -- no inverse-then-forward transform
+  if (A.fc_on && A.nf3) {
+    const FcArgs& F = A.fc;
+    float2* dst = F.T.X + ((int64_t)grp.l0 * F.T.K + wrap_slot(n, F.T.K)) * P;
+    for (int k = tid; k < P; k += kThreads) dst[k] = Y[k];
+  }
+
   // 3. inverse real FFT of the group's outputs, keep the last B samples, add
   //    the later tiers' contributions from their output rings (and clear
   //    them), emit
   irfft_pre(Y, Xa, P, tw + P, grp.nl);
-  float2* z = fft_stockham<true>(Xa, Xb, P, logP, tw, grp.nl);
+  float2* z = fft_any<true>(Xa, Xb, P, logP, T.r3, tw, grp.nl);
   const float scale = 1.0f / (float)(2 * P);
   auto emit = [&](int e, float y0, float y1) {
-    const int g = e / half, m = half + (e - g * half);
+    const int g = e / hb, m = m0 + (e - g * hb);
     const int l = grp.l0 + g;
-    const int i = 2 * (m - half);
+    const int i = 2 * (m - m0);
     const float2 v = z[g * P + m];
     const float o0 = y0 + v.x * scale, o1 = y1 + v.y * scale;
     A.out[(int64_t)l * A.B + i] = o0;
@@ -710,7 +729,7 @@ __device__ void head_work(const KArgs& A, int64_t n, const Group& grp, int gsel,
     }
   };
   auto clear_rings = [&](int e) {
-    const int g = e / half, j = 2 * (e - g * half);
+    const int g = e / hb, j = 2 * (e - g * hb);
     for (int t = 1; t < A.n_tiers; ++t) {
       float* ring = A.tier[t].oring + (int64_t)(grp.l0 + g) * (A.ring_mask + 1);
       ring[(n * A.B + j) & A.ring_mask] = 0.f;
@@ -735,7 +754,7 @@ __device__ void head_work(const KArgs& A, int64_t n, const Group& grp, int gsel,
     }
   } else {
     for (int e = tid; e < eo; e += kThreads) {
-      const int g = e / half, j = 2 * (e - g * half);
+      const int g = e / hb, j = 2 * (e - g * hb);
       float y0 = 0.f, y1 = 0.f;
       for (int t = 1; t < A.n_tiers; ++t) {
         const float* ring = A.tier[t].oring + (int64_t)(grp.l0 + g) * (A.ring_mask + 1);
@@ -767,7 +786,7 @@ __device__ void head_work(const KArgs& A, int64_t n, const Group& grp, int gsel,
   //    its window [y_l(n-1), y_l(n)] is transformed here, where y_l(n) already
   //    is, into the feedback delay line (slot n), and y_l(n) goes to its
   //    history -- the feedback launch needs no transform of its own
-  if (!A.fc_on) return;
+  if (!A.fc_on || A.nf3) return;
   __syncthreads();
   {
     const FcArgs& F = A.fc;
@@ -827,16 +846,20 @@ __device__ void fc_head_work(const KArgs& A, int64_t n, int j, float2* lds) {
     }
     return acc;
   };
-  // threads split into 256 / P groups (at least one) over bins and inputs
-  const int ng = P >= kThreads ? 1 : kThreads / P;
-  const int tg = tid / (P >= kThreads ? kThreads : P);
-  for (int k = tid % (P >= kThreads ? kThreads : P); k < P; k += (P >= kThreads ? kThreads : P)) {
-    float2 acc = term(k, tg, ng);
-    const int per = (g0.nslot + ng - 1) / ng;
-    const int a0 = min(g0.nslot, tg * per), a1 = min(g0.nslot, a0 + per);
+  // threads split into floor(256 / P) groups (at least one) over bins and
+  // inputs; with P not dividing 256 the remaining threads idle
+  const int span = P >= kThreads ? kThreads : P;
+  const int ng = kThreads / span;
+  const int tg = tid / span;
+  if (tg < ng) {
+    for (int k = tid % span; k < P; k += span) {
+      float2 acc = term(k, tg, ng);
+      const int per = (g0.nslot + ng - 1) / ng;
+      const int a0 = min(g0.nslot, tg * per), a1 = min(g0.nslot, a0 + per);
 #pragma unroll 8
-    for (int sl = a0; sl < a1; ++sl) acc = cadd(acc, base[sl * stride + k]);
-    if (ng == 1) Y[k] = acc; else scratch[tid] = acc;
+      for (int sl = a0; sl < a1; ++sl) acc = cadd(acc, base[sl * stride + k]);
+      if (ng == 1) Y[k] = acc; else scratch[tid] = acc;
+    }
   }
   __syncthreads();
   if (ng > 1) {
@@ -848,12 +871,12 @@ __device__ void fc_head_work(const KArgs& A, int64_t n, int j, float2* lds) {
     __syncthreads();
   }
   irfft_pre(Y, Xa, P, tw + P);
-  float2* z = fft_stockham<true>(Xa, Xb, P, logP, tw);
+  float2* z = fft_any<true>(Xa, Xb, P, logP, T.r3, tw);
   const float scale = 1.0f / (float)(2 * P);
-  const int half = P >> 1;
+  const int m0 = P - (A.B >> 1);  // the last B of the 2P samples
   float* cj = F.c + (int64_t)j * A.B;
-  for (int m = half + tid; m < P; m += kThreads) {
-    const int i = 2 * (m - half);
+  for (int m = m0 + tid; m < P; m += kThreads) {
+    const int i = 2 * (m - m0);
     __hip_atomic_store(cj + i, z[m].x * scale, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     __hip_atomic_store(cj + i + 1, z[m].y * scale, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }
@@ -1257,7 +1280,7 @@ __device__ __forceinline__ void store_bin(bf16c_t* H, int64_t i, float2 v, int*)
 
 template <typename HT>
 __global__ __launch_bounds__(kThreads) void k_spectra(const float* taps, const SpecRow* rows,
-                                                      HT* H, int P, int logP,
+                                                      HT* H, int P, int logP, int r3,
                                                       const float2* tw, int* range) {
   extern __shared__ float2 lds[];
   float2* a = lds;
@@ -1269,7 +1292,7 @@ __global__ __launch_bounds__(kThreads) void k_spectra(const float* taps, const S
                        i1 < row.len ? taps[row.src + i1] : 0.f);
   }
   __syncthreads();
-  float2* z = fft_stockham<false>(a, b, P, logP, tw);
+  float2* z = fft_any<false>(a, b, P, logP, r3, tw);
   float2* x = (z == a) ? b : a;
   rfft_post(z, x, P, tw + P);
   for (int k = threadIdx.x; k < P; k += kThreads) store_bin(H, row.dst * P + k, x[k], range);

@@ -95,6 +95,8 @@ struct TierHost {
   float2* partial = nullptr;
   float2* tw = nullptr;
   float* oring = nullptr;
+  int span = 0;              // filter taps per partition (P, or B when r3)
+  int r3 = 0;                // n_f = 3B first tier: P = 3B/2 bins, 3B-point transforms
   float2* tfwd = nullptr;    // tiers >= 1: transform scratch [Q][P] and [L][P]
   float2* tinv = nullptr;
   int nslots = 0;
@@ -305,17 +307,17 @@ BlockKernel block_kernel(int dtype, int G, bool nt) {
 }
 
 hipError_t launch_spectra(int dtype, dim3 grid, size_t lds, hipStream_t s, const float* taps,
-                          const SpecRow* rows, void* H, int P, int logP, const float2* tw,
+                          const SpecRow* rows, void* H, int P, int logP, int r3, const float2* tw,
                           int* range) {
   if (dtype == RTA_FP32)
     hipLaunchKernelGGL(k_spectra<float2>, grid, dim3(kThreads), lds, s, taps, rows,
-                       static_cast<float2*>(H), P, logP, tw, range);
+                       static_cast<float2*>(H), P, logP, r3, tw, range);
   else if (dtype == RTA_FP16)
     hipLaunchKernelGGL(k_spectra<f16c_t>, grid, dim3(kThreads), lds, s, taps, rows,
-                       static_cast<f16c_t*>(H), P, logP, tw, range);
+                       static_cast<f16c_t*>(H), P, logP, r3, tw, range);
   else
     hipLaunchKernelGGL(k_spectra<bf16c_t>, grid, dim3(kThreads), lds, s, taps, rows,
-                       static_cast<bf16c_t*>(H), P, logP, tw, range);
+                       static_cast<bf16c_t*>(H), P, logP, r3, tw, range);
   return hipGetLastError();
 }
 
@@ -347,7 +349,7 @@ int validate(double fs, int32_t block, const rta_scheme* scheme, int32_t n_in, i
   if (n_in < 1 || n_out < 1 || (int64_t)n_in * n_out > (1 << 20)) return RTA_E_ARG;
   if (filters == nullptr || lengths == nullptr) return RTA_E_ARG;
   if (spectra != RTA_FP32 && spectra != RTA_FP16 && spectra != RTA_BF16) return RTA_E_ARG;
-  if (flags & ~RTA_FLAG_SPIKE) return RTA_E_ARG;
+  if (flags & ~(RTA_FLAG_SPIKE | RTA_FLAG_NF3)) return RTA_E_ARG;
   int64_t max_len = 0;
   for (int64_t i = 0; i < (int64_t)n_in * n_out; ++i) {
     if (lengths[i] < 0 || lengths[i] > (int64_t(1) << 31)) return RTA_E_ARG;
@@ -369,6 +371,7 @@ int validate(double fs, int32_t block, const rta_scheme* scheme, int32_t n_in, i
   }
   const int T = (int)size.size();
   if (size[0] != block) return RTA_E_ARG;
+  if ((flags & RTA_FLAG_NF3) && T != 1) return RTA_E_ARG;  // uniform partitions only
   int64_t off = 0;
   for (int t = 0; t < T; ++t) {
     if (!is_pow2(size[t]) || size[t] % block != 0 || size[t] > (1 << 13)) return RTA_E_ARG;
@@ -495,7 +498,8 @@ int build_plan(rta_ctx* c, Plan& plan) {
     // so an output group owns nslice-fold fewer partial slots for the heads
     // to reduce; a wave still reads whole 16-byte-per-lane segments of
     // 64 / (W / C) rows
-    const int Wmax = std::min(T.P, kThreads * C);
+    // (a power of two dividing P: with n_f = 3B, P = 3B/2 gives thirds)
+    const int Wmax = std::min(T.r3 ? T.P / 3 : T.P, kThreads * C);
     const int W = std::max(C, Wmax / std::max(1, c->bin_slices)), nslice = T.P / W;
     int64_t total_rows = 0;
     for (const Group& gr : plan.groups)
@@ -812,6 +816,7 @@ KArgs make_args(const rta_ctx* c, const float* in, float* out, int64_t n) {
     d.tfwd = T.tfwd;
     d.tinv = T.tinv;
     d.lg1 = tier_lg1(T.logP);
+    d.r3 = T.r3;
     d.offset = T.offset;
     d.P = T.P;
     d.logP = T.logP;
@@ -862,6 +867,7 @@ KArgs make_args(const rta_ctx* c, const float* in, float* out, int64_t n) {
     F.T.offset = 0;
     F.T.P = T.P;
     F.T.logP = T.logP;
+    F.T.r3 = T.r3;
     F.T.K = T.K;
     F.T.nslots = std::max(1, T.nslots);
     F.T.r = 1;
@@ -881,6 +887,7 @@ KArgs make_args(const rta_ctx* c, const float* in, float* out, int64_t n) {
     F.wait_polls = c->fc_wait_polls;
     F.wait_bias = c->fc_wait_bias;
     a.fc_on = 1;
+    a.nf3 = T.r3;
     a.sub = c->d_c;
   }
   return a;
@@ -1091,7 +1098,7 @@ int run_spectra(rta_ctx* c, const std::vector<SpecJob>& jobs, hipStream_t s, flo
       HIP_TRY(c, hipMemcpyAsync(d_rows, rows.data(), sizeof(SpecRow) * rows.size(),
                                 hipMemcpyHostToDevice, s));
       HIP_TRY(c, launch_spectra(c->dtype, dim3((unsigned)rows.size()), lds, s, d_stage, d_rows, T.H,
-                                P, T.logP, T.tw, d_range));
+                                P, T.logP, T.r3, T.tw, d_range));
       HIP_TRY(c, hipStreamSynchronize(s));
       rows.clear();
       host_stage.clear();
@@ -1100,7 +1107,7 @@ int run_spectra(rta_ctx* c, const std::vector<SpecJob>& jobs, hipStream_t s, flo
     int st;
     for (const SpecJob& j : jobs) {
       if (j.tier != t || j.kp == 0) continue;
-      const int64_t a0 = T.offset, a1 = std::min(j.len, T.offset + (int64_t)j.kp * P);
+      const int64_t a0 = T.offset, a1 = std::min(j.len, T.offset + (int64_t)j.kp * T.span);
       const int64_t n = std::max<int64_t>(0, a1 - a0);
       if (n > stage_floats || j.kp > row_cap) return RTA_E_STATE;
       if ((int64_t)host_stage.size() + n > stage_floats || (int64_t)rows.size() + j.kp > row_cap)
@@ -1109,8 +1116,8 @@ int run_spectra(rta_ctx* c, const std::vector<SpecJob>& jobs, hipStream_t s, flo
       if (n > 0) host_stage.insert(host_stage.end(), j.taps + a0, j.taps + a1);
       for (int p = 0; p < j.kp; ++p) {
         SpecRow r{};
-        r.src = base + (int64_t)p * P;
-        r.len = (int32_t)std::max<int64_t>(0, std::min<int64_t>(P, n - (int64_t)p * P));
+        r.src = base + (int64_t)p * T.span;
+        r.len = (int32_t)std::max<int64_t>(0, std::min<int64_t>(T.span, n - (int64_t)p * T.span));
         r.dst = j.row + p;
         rows.push_back(r);
       }
@@ -1128,7 +1135,7 @@ int build_spectra(rta_ctx* c, const float* const* filters, const int64_t* length
   for (int64_t i = 0; i < (int64_t)c->Q * c->L; ++i) max_len = std::max(max_len, lengths[i]);
   const int64_t stage_floats = std::max<int64_t>(max_len, kStageBytes / 4);
   // a batch holds at most stage_floats taps, hence at most this many rows
-  const int64_t row_cap = stage_floats / c->tier[0].P + (int64_t)c->Q * c->L + 1;
+  const int64_t row_cap = stage_floats / c->tier[0].span + (int64_t)c->Q * c->L + 1;
   TmpDev stage, drows, drange;
   if (hipMalloc(&stage.p, sizeof(float) * (size_t)stage_floats) != hipSuccess ||
       hipMalloc(&drows.p, sizeof(SpecRow) * (size_t)row_cap) != hipSuccess ||
@@ -1241,7 +1248,7 @@ int serve_lists(rta_ctx* c, Plan& plan) {
   activate(c, sv->dev[0]);
   // admissions: staging for one source's taps and spectrum rows
   sv->stage_floats = std::max<int64_t>(sv->cfg.max_taps, kStageBytes / 4);
-  sv->row_cap = sv->stage_floats / c->tier[0].P + c->L + 1;
+  sv->row_cap = sv->stage_floats / c->tier[0].span + c->L + 1;
   if ((st = dev_alloc(c, &sv->d_stage, (size_t)sv->stage_floats)) != RTA_OK) return st;
   if ((st = dev_alloc(c, &sv->d_rows, (size_t)sv->row_cap)) != RTA_OK) return st;
   if ((st = dev_alloc(c, &sv->d_range, 1)) != RTA_OK) return st;
@@ -1281,6 +1288,12 @@ int create_impl(rta_ctx* c, const std::vector<int>& size, const std::vector<int>
     TierHost& T = c->tier[t];
     T.P = size[t];
     T.logP = ilog2(T.P);
+    T.span = T.P;
+    if (c->flags & RTA_FLAG_NF3) {  // validated: one tier, size B
+      T.r3 = 1;
+      T.P = 3 * c->B / 2;
+      T.logP = ilog2(c->B / 2);
+    }
     T.offset = off;
     T.row.assign((size_t)c->Q * c->L, -1);
     T.kp.assign((size_t)c->Q * c->L, 0);
@@ -1289,7 +1302,7 @@ int create_impl(rta_ctx* c, const std::vector<int>& size, const std::vector<int>
     for (int l = 0; l < c->L; ++l)
       for (int q = 0; q < c->Q; ++q) {
         const int64_t len = lengths[q * c->L + l];
-        int64_t need = len > off ? (len - off + T.P - 1) / T.P : 0;
+        int64_t need = len > off ? (len - off + T.span - 1) / T.span : 0;
         if (count[t] > 0) need = std::min<int64_t>(need, count[t]);
         const int pair = l * c->Q + q;
         kmax = std::max<int>(kmax, (int)need);
@@ -1302,7 +1315,7 @@ int create_impl(rta_ctx* c, const std::vector<int>& size, const std::vector<int>
       }
     T.count = count[t] > 0 ? count[t] : kmax;
     T.K = std::max(t == 0 ? c->min_ring : 1, kmax);
-    off += (int64_t)T.count * T.P;
+    off += (int64_t)T.count * T.span;
     if (sv != nullptr) {
       T.kcap = kmax;
       const int64_t full = (int64_t)c->Q * c->L * kmax;
@@ -1310,7 +1323,7 @@ int create_impl(rta_ctx* c, const std::vector<int>& size, const std::vector<int>
       rows = std::min(rows, full);
       sv->arena[t].reset(rows);
     }
-    const double per_block = (double)c->B / T.P;  // a tier's frame recurs every P/B blocks
+    const double per_block = (double)c->B / T.span;  // a tier's frame recurs every P/B blocks
     c->spectra_bytes += rows * T.P * (int64_t)eb;
     c->h_bytes += (double)rows * T.P * eb * per_block;
     c->cmacs += (double)rows * T.P * per_block;
@@ -2201,6 +2214,7 @@ int rta_query(rta_ctx* c, rta_info* info) {
   info->feedback_paths = c->fc != nullptr ? 1 : 0;
   info->feedback_fused = c->fc != nullptr && c->fc_fused ? 1 : 0;
   info->spectra_nontemporal = c->nt ? 1 : 0;
+  info->fft_size = 2 * c->tier[0].P;
   return c->poisoned ? RTA_E_DEVICE : RTA_OK;
 }
 
@@ -2223,8 +2237,12 @@ int rta_set_feedback(rta_ctx* c, const float* const* fb, const int64_t* lengths,
         ft[(int64_t)l * c->Q + q] = fb[(int64_t)q * c->L + l];
         lt[(int64_t)l * c->Q + q] = lengths[(int64_t)q * c->L + l];
       }
-    const int st = validate(c->fs, c->B, nullptr, c->L, c->Q, ft.data(), lt.data(), spectra, 0, size, count);
+    const int st = validate(c->fs, c->B, nullptr, c->L, c->Q, ft.data(), lt.data(), spectra,
+                            c->flags & RTA_FLAG_NF3, size, count);
     if (st != RTA_OK) return st;
+    // n_f = 3B hands the synthesis spectra to the feedback filters inside the
+    // block launch: same spectrum type required
+    if ((c->flags & RTA_FLAG_NF3) && spectra != c->dtype) return RTA_E_UNSUPPORTED;
   }
   HIP_TRY(c, hipDeviceSynchronize());
   c->config_gen += 1;  // graphs captured so far no longer match
@@ -2246,8 +2264,8 @@ int rta_set_feedback(rta_ctx* c, const float* const* fb, const int64_t* lengths,
     tu.tail_items = 512;
     tu.bin_slices = 8;
     rta_ctx* fc = nullptr;
-    int st = create_ctx(&fc, c->fs, c->B, size, count, c->L, c->Q, ft.data(), lt.data(), spectra, 0, &tu,
-                        nullptr, 3);
+    int st = create_ctx(&fc, c->fs, c->B, size, count, c->L, c->Q, ft.data(), lt.data(), spectra,
+                        c->flags & RTA_FLAG_NF3, &tu, nullptr, 3);
     if (st != RTA_OK) return st;
     c->fc = fc;
     if (c->d_y == nullptr) {
@@ -2267,6 +2285,13 @@ int rta_set_feedback(rta_ctx* c, const float* const* fb, const int64_t* lengths,
     if (c->fc_fused && c->lds_fused > 65536)
       HIP_TRY(c, hipFuncSetAttribute(reinterpret_cast<const void*>(block_kernel(c->dtype, c->G, c->nt)),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_fused));
+    if ((c->flags & RTA_FLAG_NF3) && !c->fc_fused) {  // the hand-off exists only fused
+      free_all(c->fc);
+      delete c->fc;
+      c->fc = nullptr;
+      (void)zero_state(c);
+      return RTA_E_UNSUPPORTED;
+    }
   }
   // serving: the paths belong to the slots; live sources stay, released ones
   // are freed, as rta_reset does
@@ -2444,6 +2469,7 @@ int rta_serve_create(rta_ctx** out, double fs, int32_t block, const rta_scheme* 
     return RTA_E_ARG;
   if ((int64_t)cfg->n_slots * cfg->n_out > (1 << 20)) return RTA_E_ARG;
   if (!tuning_ok(tuning)) return RTA_E_ARG;
+  if (flags & RTA_FLAG_NF3) return RTA_E_UNSUPPORTED;  // n_f = 2B only
   // the tiers are laid out for max_taps on every pair; no taps are read
   static const float dummy = 0.f;
   const int64_t np = (int64_t)cfg->n_slots * cfg->n_out;

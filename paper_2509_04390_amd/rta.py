@@ -43,6 +43,7 @@ RTA_FP32, RTA_FP16, RTA_BF16 = 0, 1, 2
 DTYPES = {"fp32": RTA_FP32, "fp16": RTA_FP16, "bf16": RTA_BF16}
 
 RTA_FLAG_SPIKE = 0x1
+RTA_FLAG_NF3 = 0x2
 RTA_MAX_TIERS = 8
 
 EXPORTED = ("rta_create", "rta_process", "rta_process_device", "rta_reset",
@@ -82,7 +83,8 @@ class rta_info(ctypes.Structure):
                 ("poisoned", ctypes.c_int32),
                 ("feedback_paths", ctypes.c_int32),
                 ("feedback_fused", ctypes.c_int32),
-                ("spectra_nontemporal", ctypes.c_int32)]
+                ("spectra_nontemporal", ctypes.c_int32),
+                ("fft_size", ctypes.c_int32)]
 
 
 class rta_tuning(ctypes.Structure):

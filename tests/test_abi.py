@@ -128,8 +128,10 @@ def _create_status(rta, fs=48000.0, block=128, scheme=None, n_in=1, n_out=1,
     # schemes: first tier must equal the block, sizes increasing powers of two
     dict(scheme=[(256, 4)]), dict(scheme=[(128, 4), (128, 0)]),
     dict(scheme=[(128, 4), (384, 0)]), dict(scheme=[(128, 0), (1024, 0)]),
-    # later tier must start at least 2*size - block into the filter
-    dict(scheme=[(128, 4), (1024, 0)]),
+    # a later tier must start at least size + 4 blocks into the filter
+    dict(scheme=[(128, 4), (1024, 0)]), dict(scheme=[(128, 11), (1024, 0)], lens=(4000,)),
+    # n_f = 3B: uniform partitions only
+    dict(flags=2, scheme=[(128, 12), (1024, 0)], lens=(4000,)),
     # a scheme that does not cover the filter
     dict(scheme=[(128, 1)], lens=(1000,)),
 ])
@@ -150,7 +152,8 @@ def test_invalid_tuning_is_rejected_before_any_device_call(rta):
     fp = ctypes.POINTER(ctypes.c_float)
     ptrs = (fp * 1)(taps.ctypes.data_as(fp))
     lengths = (ctypes.c_int64 * 1)(256)
-    for bad in (dict(outputs_per_group=3), dict(tail_items=-1), dict(tier_rows=-5)):
+    for bad in (dict(outputs_per_group=3), dict(tail_items=-1), dict(tier_rows=-5),
+                dict(spectra_loads=3)):
         ctx = ctypes.c_void_p()
         st = rta._lib.rta_create_tuned(ctypes.byref(ctx), 48000.0, 128, None, 1, 1, ptrs, lengths,
                                        0, 0, ctypes.byref(rta.make_tuning(**bad)))

@@ -43,24 +43,25 @@ def direct(cv, xb):
     return yb
 
 
-# (name, B, scheme, lens[q][l], feedback gain or None)
+# (name, B, scheme, lens[q][l], feedback gain or None, flags)
 CASES = [
-    ("uniform Q=2 L=3", 32, None, [[3000, 1200, 0], [800, 2600, 300]], None),
-    ("nupc 16/64/256", 16, [(16, 8), (64, 3), (256, 0)], [[3000, 700, 161]], None),
-    ("uniform + fused feedback", 32, None, [[2500, 900, 1700], [1300, 0, 2100]], 0.02),
+    ("uniform Q=2 L=3", 32, None, [[3000, 1200, 0], [800, 2600, 300]], None, 0),
+    ("nupc 16/64/256", 16, [(16, 8), (64, 3), (256, 0)], [[3000, 700, 161]], None, 0),
+    ("uniform + fused feedback", 32, None, [[2500, 900, 1700], [1300, 0, 2100]], 0.02, 0),
+    ("n_f=3B + fused feedback", 32, None, [[2500, 900, 1700], [1300, 0, 2100]], 0.02, 2),
 ]
 
 
 @pytest.mark.parametrize("case", range(len(CASES)))
 def test_graph_replay_equals_direct_launches(rta, case):
     import torch
-    name, B, scheme, lens, fb_gain = CASES[case]
+    name, B, scheme, lens, fb_gain, flags = CASES[case]
     Q, L = len(lens), len(lens[0])
     filt = make_filters(500 + case, lens)
     say(f"graph case {name}: B={B} scheme={scheme}")
-    with rta.Convolver(filt, B, scheme=scheme) as cv:
+    with rta.Convolver(filt, B, scheme=scheme, flags=flags) as cv:
         if fb_gain is not None:
-            fb = make_filters(510 + case, [[500, 300, 700], [0, 650, 200]])
+            fb = make_filters(512, [[500, 300, 700], [0, 650, 200]])
             fb = [[None if f is None else (f * fb_gain).astype(np.float32) for f in row]
                   for row in fb]
             cv.set_feedback(fb)
