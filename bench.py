@@ -301,15 +301,26 @@ def serve_bench(args, torch, rta, workloads) -> dict:
     }
 
 
+def host_stages(info) -> dict:
+    """The library's own timing of rta_process's host-side stages."""
+    n = max(1, info["host_calls"])
+    names = ("input_copy", "launch", "wait", "output_copy")
+    return {"calls": info["host_calls"],
+            "max_us": dict(zip(names, info["host_max_us"])),
+            "mean_us": {k: v / n for k, v in zip(names, info["host_sum_us"])},
+            "slowest_call": info["host_slowest_call"], "slowest_us": info["host_slowest_us"],
+            "waits_past_2ms": info["host_late_waits"]}
+
+
 def sweep_point(torch, rta, workloads, B, L, seconds, fs, spectra, fb_seconds=None,
-                steps=400, paced=300, seed=11):
+                steps=400, paced=300, seed=11, flags=0):
     """One point of the paper's sweeps (Sec. VI, Figs. 3-6): 1 input -> L
     outputs with `seconds`-long filters at block B; optionally feedback
     cancellation with one microphone and L feedback paths of fb_seconds.
     Returns mean device-path block time and paced host-path latency."""
     n_h = max(1, int(round(seconds * fs)))
     filt = workloads.reverb_filters(seed, 1, L, n_h, (6.0, 10.0), int(fs))
-    cv = rta.Convolver(filt, B, fs=fs, spectra=spectra)
+    cv = rta.Convolver(filt, B, fs=fs, spectra=spectra, flags=flags)
     if fb_seconds is not None:
         n_f = max(1, int(round(fb_seconds * fs)))
         fb = workloads.reverb_filters(seed + 1, 1, L, n_f, (0.3, 0.3), int(fs))
@@ -338,6 +349,7 @@ def sweep_point(torch, rta, workloads, B, L, seconds, fs, spectra, fb_seconds=No
     blocks = [np.ascontiguousarray(x[:, i * B:(i + 1) * B]) for i in range(64)]
     for i in range(16):
         rta.rta_process(cv.ctx, blocks[i], out)
+    cv.reset()  # also restarts the library's host-stage counters
     lat = []
     period = B / fs
     paced = max(20, min(paced, int(2.0 / period)))  # at most about 2 s of audio
@@ -364,7 +376,8 @@ def sweep_point(torch, rta, workloads, B, L, seconds, fs, spectra, fb_seconds=No
             "paced_p99_us": float(np.percentile(lat_us, 99)),
             "paced_max_us": float(lat_us.max()), "paced_max_at": int(np.argmax(lat_us)),
             "paced_blocks": len(lat), "xruns": int(np.sum(lat_us > deadline)),
-            "spectra_mb": info["spectra_bytes"] / 1e6}
+            "spectra_mb": info["spectra_bytes"] / 1e6, "fft_size": info["fft_size"],
+            "feedback_fused": info["feedback_fused"], "host_stages": host_stages(info)}
 
 
 def sweeps(args, torch, rta, workloads) -> dict:
@@ -375,12 +388,16 @@ def sweeps(args, torch, rta, workloads) -> dict:
     spectra = args.spectra or "fp32"
     which = args.sweep.split(",")
     if "all" in which:
-        which = ["block", "length", "outputs", "feedback"]
+        which = ["block", "length", "outputs", "feedback", "nf3"]
     grid = {
         "block": [dict(B=b, L=32, seconds=10.0) for b in (16, 32, 64, 128, 256, 512, 1024, 2048, 4096)],
         "length": [dict(B=128, L=32, seconds=s) for s in (0.1, 0.5, 1.0, 2.0, 5.0, 10.0, 15.0, 20.0)],
         "outputs": [dict(B=128, L=l, seconds=10.0) for l in (1, 2, 4, 8, 16, 32, 64, 96, 120, 128)],
         "feedback": [dict(B=128, L=32, seconds=10.0, fb_seconds=s) for s in (0.1, 0.5, 1.0, 2.0, 5.0)],
+        # Sec. V: n_f = 3B against 2B with feedback, from short filters (where
+        # the saved transforms should pay) to long ones
+        "nf3": [dict(B=128, L=32, seconds=s, fb_seconds=0.1, flags=f)
+                for s in (0.02, 0.05, 0.1, 0.2, 0.5, 1.0, 2.0, 10.0) for f in (0, rta.RTA_FLAG_NF3)],
     }
     res = {}
     for name in which:
@@ -456,7 +473,8 @@ def main(argv=None) -> int:
                     help="also time graph replay of runs of this many block launches "
                          "(rounded up to the work-list period); 0 skips it")
     ap.add_argument("--sweep", default=None,
-                    help="comma list of block,length,outputs,feedback or 'all': the paper's sweeps")
+                    help="comma list of block,length,outputs,feedback,nf3 or 'all': the paper's "
+                         "sweeps, and n_f = 3B against 2B with feedback")
     ap.add_argument("--serve", action="store_true",
                     help="serving with continuous batching (16 slots x 64 out x 12 s, B=64)")
     ap.add_argument("--serve-seconds", type=float, default=20.0)
@@ -596,6 +614,7 @@ def main(argv=None) -> int:
     if args.paced_blocks:
         plat = []
         period = B / fs
+        cv.reset()  # also restarts the library's host-stage counters
         with no_gc():
             nxt = time.perf_counter()
             for i in range(args.paced_blocks):
@@ -612,7 +631,8 @@ def main(argv=None) -> int:
                  "p50_us": float(np.percentile(plat_us, 50)),
                  "p99_us": float(np.percentile(plat_us, 99)), "max_us": float(plat_us.max()),
                  "max_at_block": int(np.argmax(plat_us)),
-                 "xruns": int(np.sum(plat_us > deadline))}
+                 "xruns": int(np.sum(plat_us > deadline)),
+                 "host_stages": host_stages(cv.info())}
 
     bytes_per_launch = (info["h_bytes_per_block"] + info["x_bytes_per_block"]
                         + info["io_bytes_per_block"])

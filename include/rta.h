@@ -130,6 +130,17 @@ typedef struct rta_info {
                                      non-temporal loads (rta_tuning)       */
     int32_t fft_size;             /* first tier's real transform length:
                                      2*block, or 3*block with RTA_FLAG_NF3 */
+    /* Host-side stages of rta_process() since create or rta_reset: calls,
+     * per stage (input copy into pinned memory, kernel launch, wait for
+     * the completion flag, output copy) the longest and the summed time in
+     * microseconds, the slowest call (index since reset, total time), and
+     * the waits that ran long enough (2 ms) to ask the stream for errors. */
+    int64_t host_calls;
+    double  host_max_us[4];
+    double  host_sum_us[4];
+    int64_t host_slowest_call;
+    double  host_slowest_us;
+    int64_t host_late_waits;
 } rta_info;
 
 /* Create a context.

@@ -365,6 +365,15 @@ __device__ void mac_item(int Qn, const DevTier& T, const Item& it,
   }
 }
 
+// Thread split of a reduction over E elements per input (bins, or bins of
+// several outputs): the 256 threads form kThreads / span groups, span the
+// largest power of two dividing E (at most 256), and each thread covers the
+// E / span elements tid mod span + i span (3 of them for the 3 * 2^m bins
+// of n_f = 3B, none idle); LDS scratch of 256 * E / span float2 combines the
+// groups in group order (reproducible).
+__host__ __device__ constexpr int red_span(int E) { return (E & -E) < kThreads ? (E & -E) : kThreads; }
+__host__ __device__ constexpr int red_scratch(int E) { return red_span(E) == kThreads ? kThreads : kThreads * (E / red_span(E)); }
+
 // Twiddle tables of tiers up to this size are staged in LDS before an FFT;
 // larger ones are read from global memory (they stay hot in L1/L2).
 constexpr int kTwLdsMaxP = 1024;
@@ -380,52 +389,14 @@ __device__ __forceinline__ const float2* stage_twiddles(const DevTier& T, float2
   return dst;
 }
 
-// Sum the group's partial slots for output g of the group into LDS `y`.
-// With P < 256 bins the 256 threads form 256/P groups that each add a
-// contiguous run of slots, then the runs are added in group order; the order
-// is fixed by (P, nslot), so results are reproducible.  `scratch` holds 256
-// float2.  Ends with a barrier.
-template <int G>
-__device__ void reduce_slots(const DevTier& T, const Group& grp, int g, float2* y,
-                             float2* scratch) {
-  const int P = T.P;
-  const int64_t stride = (int64_t)G * P;
-  const float2* base = T.partial + (int64_t)grp.slot0 * stride + (int64_t)g * P;
-  const int tid = threadIdx.x;
-  if (P >= kThreads) {
-    for (int k = tid; k < P; k += kThreads) {
-      float2 acc = make_float2(0.f, 0.f);
-#pragma unroll 16
-      for (int sl = 0; sl < grp.nslot; ++sl) acc = cadd(acc, base[sl * stride + k]);
-      y[k] = acc;
-    }
-    __syncthreads();
-    return;
-  }
-  const int ng = kThreads / P;
-  const int k = tid % P, tg = tid / P;
-  const int per = (grp.nslot + ng - 1) / ng;
-  const int s0 = min(grp.nslot, tg * per), s1 = min(grp.nslot, s0 + per);
-  float2 acc = make_float2(0.f, 0.f);
-#pragma unroll 16
-  for (int sl = s0; sl < s1; ++sl) acc = cadd(acc, base[sl * stride + k]);
-  scratch[tid] = acc;
-  __syncthreads();
-  if (tid < P) {
-    float2 t = scratch[k];
-    for (int g2 = 1; g2 < ng; ++g2) t = cadd(t, scratch[g2 * P + k]);
-    y[k] = t;
-  }
-  __syncthreads();
-}
-
 // Sum the first tier's partial slots of a whole output group, all its
 // outputs at once (elements e = g P + k are contiguous within a slot), and
 // add the p = 1 term sum_q H_{l,q,1} X_q(n-1), which needs no new spectrum.
-// With fewer than 256 elements, the threads form 256/E groups that each add
-// a contiguous run of slots, combined in group order (fixed for given E and
-// nslot, so results are reproducible).  Y: [G][P] in LDS; scratch: 256
-// float2.  Ends with a barrier.
+// When 256 does not divide into whole passes over the E elements (E < 256,
+// or E = 3 * 2^m), the threads form groups (red_span) that each add a
+// contiguous run of slots, combined in group order (fixed for given E and
+// nslot, so results are reproducible).  Y: [G][P] in LDS; scratch:
+// red_scratch(E) float2.  Ends with a barrier.
 template <typename HT, int G>
 __device__ void head_reduce(const KArgs& A, const DevTier& T, const Group& grp, int64_t n,
                             float2* Y, float2* scratch) {
@@ -451,7 +422,8 @@ __device__ void head_reduce(const KArgs& A, const DevTier& T, const Group& grp, 
     }
     return t;
   };
-  if (E >= kThreads) {
+  const int span = red_span(E);
+  if (span == kThreads) {
     for (int e = tid; e < E; e += kThreads) {
       float2 acc = p1_term(e, 0, 1);
 #pragma unroll 16
@@ -461,19 +433,17 @@ __device__ void head_reduce(const KArgs& A, const DevTier& T, const Group& grp, 
     __syncthreads();
     return;
   }
-  const int ng = kThreads / E;
-  const int e = tid % E, tg = tid / E;
-  float2 acc = make_float2(0.f, 0.f);
-  if (tg < ng) {
-    const int per = (grp.nslot + ng - 1) / ng;
-    const int s0 = min(grp.nslot, tg * per), s1 = min(grp.nslot, s0 + per);
-    acc = p1_term(e, tg, ng);  // the thread groups split the inputs
+  const int ng = kThreads / span, tg = tid / span;
+  const int per = (grp.nslot + ng - 1) / ng;
+  const int s0 = min(grp.nslot, tg * per), s1 = min(grp.nslot, s0 + per);
+  for (int e = tid % span; e < E; e += span) {
+    float2 acc = p1_term(e, tg, ng);  // the thread groups split the inputs
 #pragma unroll 16
     for (int sl = s0; sl < s1; ++sl) acc = cadd(acc, base[sl * stride + e]);
+    scratch[tg * E + e] = acc;
   }
-  scratch[tid] = acc;
   __syncthreads();
-  if (tid < E) {
+  for (int e = tid; e < E; e += kThreads) {
     float2 t = scratch[e];
     for (int g2 = 1; g2 < ng; ++g2) t = cadd(t, scratch[g2 * E + e]);
     Y[e] = t;
@@ -515,7 +485,7 @@ __host__ __device__ inline HeadLds head_lds(int P, int G, int nq) {
   h.xb = h.xa + nbuf * P;
   h.tw = h.xb + nbuf * P;
   h.scratch = h.tw + tw_lds_len(P);
-  h.total = h.scratch + kThreads;
+  h.total = h.scratch + red_scratch(P);
   return h;
 }
 
@@ -824,7 +794,7 @@ __device__ void fc_head_work(const KArgs& A, int64_t n, int j, float2* lds) {
   float2* Y = lds;
   float2* Xa = lds + P;
   float2* Xb = lds + 2 * P;
-  float2* scratch = lds + 3 * P + tw_lds_len(P);
+  float2* scratch = lds + 3 * P + tw_lds_len(P);  // red_scratch(P) float2
   const float2* tw = stage_twiddles(T, lds + 3 * P);
   const HT* H01 = reinterpret_cast<const HT*>(F.H01);
   const int64_t stride = (int64_t)G * P;
@@ -846,27 +816,24 @@ __device__ void fc_head_work(const KArgs& A, int64_t n, int j, float2* lds) {
     }
     return acc;
   };
-  // threads split into floor(256 / P) groups (at least one) over bins and
-  // inputs; with P not dividing 256 the remaining threads idle
-  const int span = P >= kThreads ? kThreads : P;
-  const int ng = kThreads / span;
-  const int tg = tid / span;
-  if (tg < ng) {
-    for (int k = tid % span; k < P; k += span) {
-      float2 acc = term(k, tg, ng);
-      const int per = (g0.nslot + ng - 1) / ng;
-      const int a0 = min(g0.nslot, tg * per), a1 = min(g0.nslot, a0 + per);
+  // threads split into groups over inputs and slots (red_span), each
+  // covering P / span bins
+  const int span = red_span(P);
+  const int ng = kThreads / span, tg = tid / span;
+  const int per = (g0.nslot + ng - 1) / ng;
+  const int a0 = min(g0.nslot, tg * per), a1 = min(g0.nslot, a0 + per);
+  for (int k = tid % span; k < P; k += span) {
+    float2 acc = term(k, tg, ng);
 #pragma unroll 8
-      for (int sl = a0; sl < a1; ++sl) acc = cadd(acc, base[sl * stride + k]);
-      if (ng == 1) Y[k] = acc; else scratch[tid] = acc;
-    }
+    for (int sl = a0; sl < a1; ++sl) acc = cadd(acc, base[sl * stride + k]);
+    if (ng == 1) Y[k] = acc; else scratch[tg * P + k] = acc;
   }
   __syncthreads();
   if (ng > 1) {
-    if (tid < P) {
-      float2 t = scratch[tid];
-      for (int g2 = 1; g2 < ng; ++g2) t = cadd(t, scratch[g2 * P + tid]);
-      Y[tid] = t;
+    for (int k = tid; k < P; k += kThreads) {
+      float2 t = scratch[k];
+      for (int g2 = 1; g2 < ng; ++g2) t = cadd(t, scratch[g2 * P + k]);
+      Y[k] = t;
     }
     __syncthreads();
   }

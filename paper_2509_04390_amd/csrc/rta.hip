@@ -146,6 +146,10 @@ struct rta_ctx {
   int32_t* phase_count = nullptr;
   Group* groups = nullptr;
   unsigned int* head_count = nullptr;
+  struct HostStages {          // rta_process host-side timing since create / reset
+    int64_t calls = 0, slowest_call = -1, late = 0;
+    double max_us[4] = {0, 0, 0, 0}, sum_us[4] = {0, 0, 0, 0}, slowest_us = 0;
+  } hs;
   int64_t* n_dev = nullptr;    // graph replay: device block counter
   int64_t n_dev_value = -1;    // what it holds once enqueued work is done (-1: unknown)
   int64_t config_gen = 0;      // bumped when the launch configuration changes
@@ -1031,6 +1035,7 @@ int launch_block(rta_ctx* c, const float* in, float* out, hipStream_t s, bool fl
 }
 
 int zero_state(rta_ctx* c) {
+  c->hs = rta_ctx::HostStages{};
   for (int t = 0; t < c->n_tiers; ++t) {
     TierHost& T = c->tier[t];
     HIP_TRY(c, hipMemsetAsync(T.X, 0, sizeof(float2) * (size_t)c->Q * T.K * T.P, c->stream));
@@ -2040,20 +2045,23 @@ int rta_create(rta_ctx** out, double fs, int32_t block, const rta_scheme* scheme
 int rta_process(rta_ctx* c, const float* in, float* out) {
   if (c == nullptr || in == nullptr || out == nullptr) return RTA_E_ARG;
   if (c->poisoned) return RTA_E_DEVICE;
+  using clk = std::chrono::steady_clock;
+  const clk::time_point ta = clk::now();
   std::memcpy(c->h_in, in, sizeof(float) * (size_t)c->Q * c->B);
   const int64_t want = c->block + 1;
+  const clk::time_point tb = clk::now();
   int st = launch_block(c, c->m_in, c->m_out, c->stream, true);
   if (st != RTA_OK) return st;
   // spin until the last head has raised the flag; the tail workgroups of the
   // same launch keep running.  No runtime call on the normal path: only once
   // the flag is 2 ms late is the stream asked for errors (then every 1 ms),
   // so a failed launch cannot spin forever.
-  using clk = std::chrono::steady_clock;
   const clk::time_point t0 = clk::now();
   clk::time_point next_check = t0 + std::chrono::milliseconds(2);
   for (uint64_t i = 1;; ++i) {
     if (__atomic_load_n(c->h_flag, __ATOMIC_ACQUIRE) == want) break;
     if ((i & 255) == 0 && clk::now() >= next_check) {
+      if (next_check == t0 + std::chrono::milliseconds(2)) c->hs.late += 1;
       const hipError_t e = hipStreamQuery(c->stream);
       if (e == hipSuccess) {
         if (__atomic_load_n(c->h_flag, __ATOMIC_ACQUIRE) == want) break;
@@ -2065,7 +2073,22 @@ int rta_process(rta_ctx* c, const float* in, float* out) {
     }
   }
   if ((st = device_status(c)) != RTA_OK) return st;
+  const clk::time_point td = clk::now();
   std::memcpy(out, c->h_out, sizeof(float) * (size_t)c->L * c->B);
+  const clk::time_point te = clk::now();
+  const clk::time_point ts[5] = {ta, tb, t0, td, te};
+  rta_ctx::HostStages& h = c->hs;
+  for (int k = 0; k < 4; ++k) {
+    const double us = std::chrono::duration<double, std::micro>(ts[k + 1] - ts[k]).count();
+    h.max_us[k] = std::max(h.max_us[k], us);
+    h.sum_us[k] += us;
+  }
+  const double tot = std::chrono::duration<double, std::micro>(te - ta).count();
+  if (tot > h.slowest_us) {
+    h.slowest_us = tot;
+    h.slowest_call = h.calls;
+  }
+  h.calls += 1;
   return RTA_OK;
 }
 
@@ -2215,6 +2238,14 @@ int rta_query(rta_ctx* c, rta_info* info) {
   info->feedback_fused = c->fc != nullptr && c->fc_fused ? 1 : 0;
   info->spectra_nontemporal = c->nt ? 1 : 0;
   info->fft_size = 2 * c->tier[0].P;
+  info->host_calls = c->hs.calls;
+  for (int k = 0; k < 4; ++k) {
+    info->host_max_us[k] = c->hs.max_us[k];
+    info->host_sum_us[k] = c->hs.sum_us[k];
+  }
+  info->host_slowest_call = c->hs.slowest_call;
+  info->host_slowest_us = c->hs.slowest_us;
+  info->host_late_waits = c->hs.late;
   return c->poisoned ? RTA_E_DEVICE : RTA_OK;
 }
 
@@ -2275,7 +2306,7 @@ int rta_set_feedback(rta_ctx* c, const float* const* fb, const int64_t* lengths,
     }
     // fused when both store the same spectrum type and the launch's LDS fits
     const int P = c->tier[0].P, C = vec_bins(c->dtype);
-    const size_t fc_head = sizeof(float2) * (size_t)(3 * P + tw_lds_len(P) + kThreads);
+    const size_t fc_head = sizeof(float2) * (size_t)(3 * P + tw_lds_len(P) + red_scratch(P));
     const size_t fc_tail = sizeof(float2) * (size_t)kThreads * C * c->G;
     c->lds_fused = std::max(c->lds, std::max(fc_head, fc_tail));
     int max_lds = 0;

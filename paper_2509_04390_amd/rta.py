@@ -84,7 +84,13 @@ class rta_info(ctypes.Structure):
                 ("feedback_paths", ctypes.c_int32),
                 ("feedback_fused", ctypes.c_int32),
                 ("spectra_nontemporal", ctypes.c_int32),
-                ("fft_size", ctypes.c_int32)]
+                ("fft_size", ctypes.c_int32),
+                ("host_calls", ctypes.c_int64),
+                ("host_max_us", ctypes.c_double * 4),
+                ("host_sum_us", ctypes.c_double * 4),
+                ("host_slowest_call", ctypes.c_int64),
+                ("host_slowest_us", ctypes.c_double),
+                ("host_late_waits", ctypes.c_int64)]
 
 
 class rta_tuning(ctypes.Structure):
@@ -351,7 +357,9 @@ def rta_query(ctx) -> dict:
     d = {}
     for name, _ in rta_info._fields_:
         v = getattr(info, name)
-        d[name] = list(v)[:info.n_tiers] if hasattr(v, "__len__") else v
+        if hasattr(v, "__len__"):
+            v = list(v)[:info.n_tiers] if name.startswith("tier_") else list(v)
+        d[name] = v
     return d
 
 

@@ -303,3 +303,22 @@ def test_target_point_sampled(rta, spectra, limit):
                           rng.integers(576000, n, 40)])
     ref = oracle.direct_at(x, filt, idx)
     check_db(y[:, idx], ref, limit, f"target/{spectra}")
+
+
+def test_host_stage_counters(rta):
+    """rta_process times its host-side stages; rta_reset restarts the counts."""
+    B = 64
+    filt = make_filters(90, [[1000, 300]])
+    x = padded_signal(91, 1, 12, B, 1000)
+    with rta.Convolver(filt, B) as cv:
+        cv.run(x)
+        info = cv.info()
+        n = x.shape[1] // B
+        assert info["host_calls"] == n
+        assert all(m >= 0 for m in info["host_max_us"]) and info["host_max_us"][2] > 0
+        assert 0 <= info["host_slowest_call"] < n and info["host_slowest_us"] > 0
+        assert sum(info["host_sum_us"]) <= n * info["host_slowest_us"] + 1e-6
+        say(f"  host stages max us: {info['host_max_us']}, waits past 2 ms {info['host_late_waits']}")
+        cv.reset()
+        info = cv.info()
+        assert info["host_calls"] == 0 and info["host_slowest_call"] == -1
