@@ -169,11 +169,93 @@ __device__ float2* fft_stockham3(float2* a, float2* b, int N, int m,
   return a;
 }
 
-// Complex FFT of length N = 2^logN (r3 = 0) or N = 3 * 2^logN (r3 = 1).
+// Bit reversal of s over log2(V) bits, V in {1, 2, 4, 8}.
+template <int V>
+__device__ __forceinline__ constexpr int brev_small(int s) {
+  return V == 1 ? 0 : V == 2 ? s : V == 4 ? ((s & 1) << 1) | (s >> 1)
+                                        : ((s & 1) << 2) | (s & 2) | (s >> 2);
+}
+
+// One N = 64 V-point transform (V in {1, 2}; brev_small and the in-lane
+// stage also cover 4 and 8) by one wavefront, without barriers: lane i
+// holds x[64 v + i] (v < V) in registers, with n = 64 v + i and
+// k = k1 + V k2 the transform factors as
+//   X[k1 + V k2] = sum_i W_64^{i k2} W_N^{i k1} sum_v x[64 v + i] W_V^{v k1}:
+// a V-point DIF in each lane's registers, the twiddles W_N^{i k1}, then a
+// 64-point radix-2 DIF across the lanes whose butterfly partners are
+// exchanged with lane shuffles (distance 32, 16, ..., 1).  Lane i then holds
+// k2 = bitrev6(i) and register s holds k1 = bitrev(s); each value is written
+// to its natural place in `dst`.  `tw` = W_N^j (j < N); INV conjugates.
+template <bool INV, int V>
+__device__ __forceinline__ void fft_wave_one(const float2* __restrict__ src, float2* __restrict__ dst,
+                                             int N, const float2* __restrict__ tw, int lane) {
+  auto twid = [&](int j) {
+    float2 w = tw[j];
+    if (INV) w.y = -w.y;
+    return w;
+  };
+  float2 r[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) r[v] = src[64 * v + lane];
+#pragma unroll
+  for (int h = V / 2; h >= 1; h /= 2) {
+#pragma unroll
+    for (int blk = 0; blk < V; blk += 2 * h) {
+#pragma unroll
+      for (int j = 0; j < h; ++j) {
+        const float2 p = r[blk + j], q = r[blk + j + h];
+        r[blk + j] = cadd(p, q);
+        r[blk + j + h] = j == 0 ? csub(p, q) : cmul(csub(p, q), twid(j * (V / (2 * h)) * 64));
+      }
+    }
+  }
+#pragma unroll
+  for (int s = 1; s < V; ++s) r[s] = cmul(r[s], twid(lane * brev_small<V>(s)));
+#pragma unroll
+  for (int h = 32; h >= 1; h >>= 1) {
+    const bool hi = (lane & h) != 0;
+    const float2 w = twid((lane & (h - 1)) * (N / (2 * h)));
+#pragma unroll
+    for (int s = 0; s < V; ++s) {
+      const float2 p = make_float2(__shfl_xor(r[s].x, h), __shfl_xor(r[s].y, h));
+      r[s] = hi ? cmul(csub(p, r[s]), w) : cadd(r[s], p);
+    }
+  }
+  const int k2 = (int)(__brev((unsigned int)lane) >> 26);
+#pragma unroll
+  for (int s = 0; s < V; ++s) dst[brev_small<V>(s) + V * k2] = r[s];
+}
+
+// Batched complex FFT of length N in {64, 128}: transform t is run
+// by wavefront t mod (blockDim.x / 64), reading `a` and writing `b` (LDS,
+// [nb][N] each); the stages inside a transform need no workgroup barrier.
+// Returns `b`; ends with a barrier.
+template <bool INV>
+__device__ __forceinline__ float2* fft_wave(float2* a, float2* b, int N, const float2* __restrict__ tw, int nb) {
+  const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  for (int t = threadIdx.x >> 6; t < nb; t += nw) {
+    const float2* src = a + t * N;
+    float2* dst = b + t * N;
+    if (N == 64)
+      fft_wave_one<INV, 1>(src, dst, N, tw, lane);
+    else
+      fft_wave_one<INV, 2>(src, dst, N, tw, lane);
+  }
+  __syncthreads();
+  return b;
+}
+
+// Complex FFT of length N = 2^logN (r3 = 0) or N = 3 * 2^logN (r3 = 1):
+// lengths 64 and 128 (blocks of 64 and 128 samples) by wavefronts with lane
+// shuffles, the others by the LDS Stockham routines.  (Longer wave variants,
+// 4 or 8 values per lane, raised the block kernel to 164 VGPRs for every
+// workgroup, the bandwidth-bound tails included.)
 template <bool INV>
 __device__ __forceinline__ float2* fft_any(float2* a, float2* b, int N, int logN, int r3,
                                            const float2* __restrict__ tw, int nb = 1) {
-  return r3 ? fft_stockham3<INV>(a, b, N, logN, tw, nb) : fft_stockham<INV>(a, b, N, logN, tw, nb);
+  if (r3) return fft_stockham3<INV>(a, b, N, logN, tw, nb);
+  if (N == 64 || N == 128) return fft_wave<INV>(a, b, N, tw, nb);
+  return fft_stockham<INV>(a, b, N, logN, tw, nb);
 }
 
 // Packed spectra of nb real signals of 2P samples whose complex FFTs Z

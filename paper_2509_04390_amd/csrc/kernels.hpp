@@ -771,7 +771,7 @@ __device__ void head_work(const KArgs& A, int64_t n, const Group& grp, int gsel,
     }
     __syncthreads();
     for (int i = tid; i < A.B; i += kThreads) hl[(n * A.B + i) & F.hist_mask] = yn[i];
-    float2* zf = fft_stockham<false>(Xa, Xb, P, logP, tw);
+    float2* zf = fft_any<false>(Xa, Xb, P, logP, 0, tw);
     float2* xf = (zf == Xa) ? Xb : Xa;
     rfft_post(zf, xf, P, tw + P);
     float2* dst = F.T.X + ((int64_t)l * F.T.K + wrap_slot(n, F.T.K)) * P;
