@@ -214,6 +214,15 @@ def serve_bench(args, torch, rta, workloads) -> dict:
                      budget_bytes=budget)
     info0, _ = srv.query()
     log(f"arena {info0['arena_bytes'] / 1e9:.2f} GB, budget {budget / 1e9:.2f} GB/block")
+    fb_taps = args.serve_feedback_taps
+    if fb_taps:
+        # feedback cancellation (Sec. III-A Eq. 3): paths from the 64
+        # loudspeakers to the 16 microphone slots, weak enough to keep the
+        # loop gain below one; same spectrum type as the synthesis (fused)
+        paths = workloads.reverb_filters(wl.seed + 99, wl.n_in, L, fb_taps, 0.1)
+        srv.set_feedback([[(0.002 * p).astype(np.float32) for p in row] for row in paths],
+                         spectra=spectra)
+        log(f"feedback: {L} -> {wl.n_in} x {fb_taps} taps, fused {srv.info()['feedback_fused']}")
 
     events = sorted([(a, 0, i) for i, (a, _, _) in enumerate(arrivals)] +
                     [(e, 1, i) for i, (_, e, _) in enumerate(arrivals)])
@@ -284,7 +293,11 @@ def serve_bench(args, torch, rta, workloads) -> dict:
                                 f"filters, block {B}, {spectra} spectra, "
                                 f"{'uniform partitions' if scheme is None else args.scheme}; "
                                 f"Poisson arrivals {args.serve_rate}/s, Exp({args.serve_life} s) "
-                                f"lifetimes, {args.serve_seconds} s"),
+                                f"lifetimes, {args.serve_seconds} s; feedback cancellation "
+                                f"{L} -> {wl.n_in} x {fb_taps} taps" if fb_taps else
+                                f"{'uniform partitions' if scheme is None else args.scheme}; "
+                                f"Poisson arrivals {args.serve_rate}/s, Exp({args.serve_life} s) "
+                                f"lifetimes, {args.serve_seconds} s; no feedback paths"),
                    "block": B, "n_in": wl.n_in, "n_out": L, "taps": taps, "spectra": spectra},
         "deadline_us": deadline,
         "latency": {"p50_us": float(np.percentile(lat_us, 50)), "p99_us": p99,
@@ -480,6 +493,8 @@ def main(argv=None) -> int:
     ap.add_argument("--serve-seconds", type=float, default=20.0)
     ap.add_argument("--serve-rate", type=float, default=8.0, help="arrivals per second")
     ap.add_argument("--serve-life", type=float, default=2.0, help="mean source lifetime, s")
+    ap.add_argument("--serve-feedback-taps", type=int, default=8192,
+                    help="feedback paths 64 -> 16 of this many taps in the serving run (0: none)")
     ap.add_argument("--serve-budget-frac", type=float, default=0.5,
                     help="admission budget: this fraction of deadline x probed bandwidth")
     args = ap.parse_args(argv)

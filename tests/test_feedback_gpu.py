@@ -215,3 +215,35 @@ def test_feedback_wait_that_gives_up_fails_the_block(rta):
         cv.process_device(xi, yo)
     assert e.value.status == rta.RTA_E_DEVICE
     cv.close()
+
+
+def test_matched_room_does_not_drift_over_60_seconds(rta):
+    """60 s of the closed loop at the cfg5 shape: 16 microphones, 64
+    loudspeakers, 8,192-tap paths, block 64 (45,000 blocks).  The room is a
+    second context with the true paths F (64 -> 16) whose output for block n
+    reaches the microphones in block n + 1; the canceller holds F^ = F, so
+    the loudspeakers must carry H^T * s alone (Sec. III-A Eq. 1-3), at the
+    end of the minute as at its start: FP32 bound at late samples, checked
+    by direct sums."""
+    B, P, L = 64, 16, 64
+    nb = 60 * 48000 // B
+    rng = np.random.default_rng(770)
+    h = weak(make_filters(771, [[int(rng.integers(200, 1000)) for _ in range(L)] for _ in range(P)]),
+             0.007)
+    f = weak(make_filters(772, [[8192] * L for _ in range(P)], rt60=0.1), 0.002)
+    room_filters = [[f[q][l] for q in range(P)] for l in range(L)]  # 64 inputs -> 16 outputs
+    s = workloads.white_noise(773, P, nb * B)
+    y = np.empty((L, nb * B), np.float32)
+    with rta.Convolver(h, B) as cv, rta.Convolver(room_filters, B) as room:
+        cv.set_feedback(f)
+        assert cv.info()["feedback_fused"] == 1
+        heard = np.zeros((P, B), np.float32)
+        for n in range(nb):
+            m = s[:, n * B:(n + 1) * B] + heard
+            yn = cv.process(m)
+            y[:, n * B:(n + 1) * B] = yn
+            heard = room.process(yn)
+    for what, lo, hi in (("first 5 s", 8192, 5 * 48000), ("last 5 s", nb * B - 5 * 48000, nb * B)):
+        idx = np.unique(rng.integers(lo, hi, 200))
+        ref = oracle.direct_at(s, h, idx)
+        check_db(y[:, idx], ref, FP32_DB, f"matched room, {what}")
