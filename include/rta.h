@@ -182,8 +182,9 @@ int rta_create(rta_ctx** out, double fs, int32_t block,
  *   spectra_loads      how the multiply-accumulate streams the spectra:
  *                      1 = non-temporal loads, 2 = ordinary loads, 0 =
  *                      default (ordinary for uniform partitions, which
- *                      re-read every row every block; non-temporal with
- *                      later tiers and for serving contexts).
+ *                      re-read every row every block, up to 384 MB of
+ *                      spectra; non-temporal beyond that, with later tiers
+ *                      and for serving contexts).
  * rta_autotune() also fills the scheme it selected (n_tiers, size, count). */
 typedef struct rta_tuning {
     int32_t outputs_per_group;

@@ -1454,12 +1454,14 @@ int create_impl(rta_ctx* c, const std::vector<int>& size, const std::vector<int>
   // reduction.  head_nq: as many inputs per pass as fit in 48 KB, at least 1.
   const int C = vec_bins(c->dtype);
   // uniform partitions re-read every spectrum row every block: ordinary
-  // loads stream them faster (measured with 123 MB and 295 MB of FP32
-  // spectra, inside and beyond the Infinity Cache); later tiers touch their
-  // rows once per frame, and serving contexts stream whatever is admitted:
-  // non-temporal loads there
+  // loads stream them faster up to a few hundred MB (measured with 61 to
+  // 295 MB of spectra, inside and beyond the 256 MB Infinity Cache), while
+  // 443 MB (4 -> 64 x U[3,12] s FP16) went faster non-temporal; later tiers
+  // touch their rows once per frame, and serving contexts stream whatever
+  // is admitted: non-temporal loads there
   c->nt = c->spectra_loads == 1 ||
-          (c->spectra_loads == 0 && (c->serve != nullptr || c->n_tiers > 1));
+          (c->spectra_loads == 0 && (c->serve != nullptr || c->n_tiers > 1 ||
+                                     c->spectra_bytes > (int64_t(384) << 20)));
   const int P0 = c->tier[0].P;
   const int fixed = head_lds(P0, 1, 1).total - 2 * P0;
   c->head_nq = std::max(1, std::min(c->Q, (6144 - fixed) / (2 * P0)));
