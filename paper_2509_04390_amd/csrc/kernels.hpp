@@ -379,6 +379,31 @@ __host__ __device__ constexpr int red_scratch(int E) { return red_span(E) == kTh
 constexpr int kTwLdsMaxP = 1024;
 __host__ __device__ constexpr int tw_lds_len(int P) { return P <= kTwLdsMaxP ? 2 * P : 0; }
 
+// Twiddles of tables up to kThreads * kTwRegs entries are loaded into
+// registers first and written to LDS later (stage_twiddles_regs /
+// store_twiddles_regs), so their global round trip overlaps the head's other
+// loads instead of preceding them.
+constexpr int kTwRegs = 2;
+struct TwRegs { float2 v[kTwRegs]; int n; };
+__device__ __forceinline__ TwRegs load_twiddles_regs(const DevTier& T) {
+  TwRegs r;
+  r.n = tw_lds_len(T.P);
+  if (r.n > kTwRegs * kThreads) r.n = 0;  // too long: stage_twiddles instead
+#pragma unroll
+  for (int i = 0; i < kTwRegs; ++i) {
+    const int j = threadIdx.x + i * kThreads;
+    if (j < r.n) r.v[i] = T.tw[j];
+  }
+  return r;
+}
+__device__ __forceinline__ void store_twiddles_regs(const TwRegs& r, float2* dst) {
+#pragma unroll
+  for (int i = 0; i < kTwRegs; ++i) {
+    const int j = threadIdx.x + i * kThreads;
+    if (j < r.n) dst[j] = r.v[i];
+  }
+}
+
 // Returns the twiddle table to use: a copy in LDS at `dst` when it fits,
 // otherwise the global table.  No barrier: the caller's next barrier
 // publishes the copy.
@@ -506,7 +531,11 @@ __device__ void head_work(const KArgs& A, int64_t n, const Group& grp, int gsel,
   float2* Xa = lds + L.xa;
   float2* Xb = lds + L.xb;
   float2* scratch = lds + L.scratch;
-  const float2* tw = stage_twiddles(T, lds + L.tw);
+  // twiddles for the FFTs: requested now, written to LDS after the partial-sum
+  // reduction (its loads then share the round trip); published by the
+  // barrier before the first FFT
+  const TwRegs twr = load_twiddles_regs(T);
+  const float2* tw = twr.n > 0 ? lds + L.tw : stage_twiddles(T, lds + L.tw);
   const HT* H01 = reinterpret_cast<const HT*>(A.H01);
 
   // 0. Prefetch.  The heads run beside the bandwidth-bound tails, so every
@@ -601,6 +630,7 @@ __device__ void head_work(const KArgs& A, int64_t n, const Group& grp, int gsel,
     return t;
   }();
   head_reduce<HT, G>(A, Tcur, grp, n, Y, scratch);
+  store_twiddles_regs(twr, lds + L.tw);
 
   // fused feedback: wait until every feedback head of this launch has
   // published c_{n-1}
@@ -795,7 +825,10 @@ __device__ void fc_head_work(const KArgs& A, int64_t n, int j, float2* lds) {
   float2* Xa = lds + P;
   float2* Xb = lds + 2 * P;
   float2* scratch = lds + 3 * P + tw_lds_len(P);  // red_scratch(P) float2
-  const float2* tw = stage_twiddles(T, lds + 3 * P);
+  // twiddles requested with the reduction's loads, written to LDS before its
+  // closing barrier
+  const TwRegs twr = load_twiddles_regs(T);
+  const float2* tw = twr.n > 0 ? lds + 3 * P : stage_twiddles(T, lds + 3 * P);
   const HT* H01 = reinterpret_cast<const HT*>(F.H01);
   const int64_t stride = (int64_t)G * P;
   const float2* base = T.partial + ((n - 1) & 1) * (int64_t)T.nslots * G * P +
@@ -828,6 +861,7 @@ __device__ void fc_head_work(const KArgs& A, int64_t n, int j, float2* lds) {
     for (int sl = a0; sl < a1; ++sl) acc = cadd(acc, base[sl * stride + k]);
     if (ng == 1) Y[k] = acc; else scratch[tg * P + k] = acc;
   }
+  store_twiddles_regs(twr, lds + 3 * P);
   __syncthreads();
   if (ng > 1) {
     for (int k = tid; k < P; k += kThreads) {
