@@ -322,3 +322,19 @@ def test_host_stage_counters(rta):
         cv.reset()
         info = cv.info()
         assert info["host_calls"] == 0 and info["host_slowest_call"] == -1
+
+
+def test_degenerate_contexts(rta):
+    """Edge cases of the method: every path absent (outputs exactly zero),
+    silence in (silence out, exactly), and a context that is created and
+    destroyed without processing a block."""
+    B = 32
+    with rta.Convolver([[None, None], [None, None]], B) as cv:
+        y = cv.run(workloads.white_noise(95, 2, 8 * B))
+    assert y.shape == (2, 8 * B) and np.all(y == 0.0)
+    filt = make_filters(96, [[700, 0, 90]])
+    with rta.Convolver(filt, B) as cv:
+        y = cv.run(np.zeros((1, 12 * B), np.float32))
+        assert np.all(y == 0.0)
+        assert cv.info()["blocks_done"] == 12
+    rta.Convolver(filt, B).close()
