@@ -137,7 +137,8 @@ struct KArgs {
   int32_t head_nq;           // inputs transformed per pass by a head
   int32_t n_head;            // head workgroups (one per output)
   int32_t head_slots;        // head part of the grid (n_head rounded up to 8)
-  int32_t pad;
+  int32_t tails_wait;        // rta_process: multiply-accumulate workgroups
+                             // start once this launch's heads are done
   int64_t n;                 // index of the block of this launch
   const Item* tier_items;    // later tiers' transform passes [n_phase][max_tier_items]
   const int32_t* tier_count; // transform items per phase
@@ -147,6 +148,7 @@ struct KArgs {
   int32_t n_groups_total;
   int32_t tier_slots;        // transform part of this launch's grid (a multiple of 8)
   int32_t pad4;
+  unsigned int* heads_done;  // heads finished so far (monotonic, agent scope)
   const void* H01;           // [L][Q][2][P] spectra of partitions 0 and 1
   unsigned int* head_count;  // heads finished in this launch (zero between)
   int64_t* done_flag;        // host-visible: n + 1 once the output is written
@@ -766,6 +768,10 @@ __device__ void head_work(const KArgs& A, int64_t n, const Group& grp, int gsel,
     }
   }
 
+  // this head's output is out: the tail workgroups of a waiting launch may
+  // start streaming (relaxed: they read nothing the heads wrote)
+  if (tid == 0) __hip_atomic_fetch_add(A.heads_done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+
   // 4. completion (rta_process only): every head makes its output visible
   //    system-wide, the last one raises the flag (only the heads count, so
   //    the host does not wait for the tail workgroups of this launch)
@@ -1167,6 +1173,22 @@ __global__ __launch_bounds__(kThreads) void k_block(const KArgs A) {
     return;
   }
   const int i = b - A.tier_slots;
+  // rta_process: the heads of this launch are the block's latency path, and
+  // they run slower on compute units that streaming tails share; the
+  // multiply-accumulate (for the next block) waits until they are done.  A
+  // bounded wait that gives up only costs time: the tails read nothing the
+  // heads write.
+  if (A.tails_wait) {
+    if (threadIdx.x == 0) {
+      const unsigned int target = (unsigned int)((n + 1) * A.n_head);
+      for (int it = 0; it < 512; ++it) {  // about 0.2 ms at most
+        if ((int)(__hip_atomic_load(A.heads_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) >= 0)
+          break;
+        __builtin_amdgcn_s_sleep(16);
+      }
+    }
+    __syncthreads();
+  }
   if (A.fc_on && i >= A.fc.tail0) {  // feedback terms p >= 2 for c_n
     const int j = i - A.fc.tail0;
     if (j >= A.fc.n_items) return;

@@ -146,6 +146,7 @@ struct rta_ctx {
   int32_t* phase_count = nullptr;
   Group* groups = nullptr;
   unsigned int* head_count = nullptr;
+  unsigned int* heads_done = nullptr;  // heads finished, all blocks (monotonic)
   struct HostStages {          // rta_process host-side timing since create / reset
     int64_t calls = 0, slowest_call = -1, late = 0;
     double max_us[4] = {0, 0, 0, 0}, sum_us[4] = {0, 0, 0, 0}, slowest_us = 0;
@@ -848,6 +849,7 @@ KArgs make_args(const rta_ctx* c, const float* in, float* out, int64_t n) {
   a.n = n;
   a.H01 = c->H01;
   a.head_count = c->head_count;
+  a.heads_done = c->heads_done;
   a.done_flag = nullptr;  // set by rta_process, which polls it
   a.tier_items = c->tier_items;
   a.tier_count = c->tier_count;
@@ -990,7 +992,15 @@ int launch_block(rta_ctx* c, const float* in, float* out, hipStream_t s, bool fl
     if (st != RTA_OK) return st;
   }
   KArgs a = make_args(c, in, out, c->block);
-  if (flag) a.done_flag = c->m_flag;
+  if (flag) {
+    a.done_flag = c->m_flag;
+    // a real-time block: its output first, when the tails stream enough to
+    // slow the heads down (measured: 1 -> 32 x 480,000 taps FP32 paced p50
+    // 41 -> 33 us, 1 -> 64 x 576,000 taps 56 -> 41 us; with the 11 MB per
+    // block of the 4 -> 64 NUPC workload the waiting tails' polls cost more
+    // than they saved)
+    a.tails_wait = c->h_bytes >= 32e6 ? 1 : 0;
+  }
   unsigned grid = 0;
   size_t lds = 0;
   block_geometry(c, c->block, a, grid, lds);
@@ -1052,6 +1062,7 @@ int zero_state(rta_ctx* c) {
   }
   HIP_TRY(c, hipMemsetAsync(c->hist, 0, sizeof(float) * (size_t)c->Q * c->hist_len, c->stream));
   HIP_TRY(c, hipMemsetAsync(c->head_count, 0, sizeof(unsigned int), c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->heads_done, 0, sizeof(unsigned int), c->stream));
   if (c->d_c) HIP_TRY(c, hipMemsetAsync(c->d_c, 0, sizeof(float) * (size_t)c->Q * c->B, c->stream));
   if (c->fc_done) HIP_TRY(c, hipMemsetAsync(c->fc_done, 0, sizeof(unsigned int), c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -1419,6 +1430,7 @@ int create_impl(rta_ctx* c, const std::vector<int>& size, const std::vector<int>
   if ((st = dev_alloc(c, &c->tier_nslot, plan.tier_nslot.size())) != RTA_OK) return st;
   if ((st = dev_alloc(c, &c->groups, plan.groups.size())) != RTA_OK) return st;
   if ((st = dev_alloc(c, &c->head_count, 1)) != RTA_OK) return st;
+  if ((st = dev_alloc(c, &c->heads_done, 1)) != RTA_OK) return st;
   HIP_TRY(c, hipMemcpy(c->tier_slot0, plan.tier_slot0.data(), sizeof(int32_t) * plan.tier_slot0.size(), hipMemcpyHostToDevice));
   HIP_TRY(c, hipMemcpy(c->tier_nslot, plan.tier_nslot.data(), sizeof(int32_t) * plan.tier_nslot.size(), hipMemcpyHostToDevice));
   HIP_TRY(c, hipMemcpy(c->groups, plan.groups.data(), sizeof(Group) * plan.groups.size(), hipMemcpyHostToDevice));
