@@ -208,8 +208,10 @@ int rta_create_tuned(rta_ctx** out, double fs, int32_t block,
 /* Autotuner.  Same arguments as rta_create(), except that a NULL scheme
  * means "choose one": the candidates are uniform partitioning and the
  * non-uniform schemes with partition ratios 8 (B, 8B, 64B) and 4 (B, 4B,
- * 16B, 64B), each tier starting exactly 2 P_t - B taps into the filter,
- * limited to tiers the longest filter reaches and to sizes <= 8192.  For
+ * 16B, 64B), partitions up to 8192 or up to 2048 samples, and a first
+ * (block-sized) tier of its minimum length or twice it; each later tier
+ * starts at max(2 P_t - B, P_t + 4B) taps rounded up to whole partitions of
+ * the tier before, limited to tiers the longest filter reaches.  For
  * every candidate scheme and tiling (G in {1, 2, 4} x tail_items in {256,
  * 512, 1024} x bin_slices in {1, 2, 4}, then spectra_loads 1 and 2 for the
  * best of those) a context is created, `blocks` blocks of zero input are run
@@ -226,8 +228,8 @@ int rta_autotune(double fs, int32_t block, const rta_scheme* scheme,
 /* rta_autotune() behind a tuning cache at `cache_path`, a text file of one
  * JSON object per line.  The key covers the device (architecture name and
  * compute-unit count), fs, block, n_in, n_out, a hash of the filter lengths
- * (not the taps), spectra, flags, blocks and the scheme (or "auto" for
- * NULL).  On a hit with a valid entry, *best / *best_us come from the file
+ * (not the taps), spectra, flags, blocks and the scheme (or "auto2", the
+ * current set of candidate schemes, for NULL).  On a hit with a valid entry, *best / *best_us come from the file
  * (*from_cache = 1; no device work); otherwise rta_autotune() runs and one
  * line is appended (*from_cache = 0).  from_cache may be NULL.  RTA_E_ARG if
  * the file cannot be appended to (the tuning is still returned).  One

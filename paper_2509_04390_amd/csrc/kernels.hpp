@@ -194,6 +194,11 @@ template <> struct HVec<float2> {
     h[1] = make_float2(v.z, v.w);
   }
   static __device__ __forceinline__ float2 load1(const float2* p) { return *p; }
+  // one element as loaded, converted where it is used (held across other
+  // work, a converted load would make the wave wait for it at once)
+  typedef float2 one_t;
+  static __device__ __forceinline__ one_t load1_raw(const float2* p) { return *p; }
+  static __device__ __forceinline__ float2 cvt1(one_t v) { return v; }
 };
 
 __device__ __forceinline__ float2 f16pair(uint32_t w) {
@@ -222,6 +227,9 @@ template <> struct HVec<f16c_t> {
     h[1] = f16pair(v.y);
   }
   static __device__ __forceinline__ float2 load1(const f16c_t* p) { return f16pair(p->bits); }
+  typedef uint32_t one_t;
+  static __device__ __forceinline__ one_t load1_raw(const f16c_t* p) { return p->bits; }
+  static __device__ __forceinline__ float2 cvt1(one_t v) { return f16pair(v); }
 };
 
 template <> struct HVec<bf16c_t> {
@@ -238,7 +246,27 @@ template <> struct HVec<bf16c_t> {
     h[1] = bf16pair(v.y);
   }
   static __device__ __forceinline__ float2 load1(const bf16c_t* p) { return bf16pair(p->bits); }
+  typedef uint32_t one_t;
+  static __device__ __forceinline__ one_t load1_raw(const bf16c_t* p) { return p->bits; }
+  static __device__ __forceinline__ float2 cvt1(one_t v) { return bf16pair(v); }
 };
+
+// Prefetched values are pinned where they are used: the empty asm takes the
+// register as it is, so the compiler cannot move arithmetic on the value up
+// to its load (where the wave would then wait for the load to return).
+__device__ __forceinline__ float pin(float v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+__device__ __forceinline__ uint32_t pin(uint32_t v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+__device__ __forceinline__ int pin(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+__device__ __forceinline__ float2 pin(float2 v) { return make_float2(pin(v.x), pin(v.y)); }
 
 __device__ __forceinline__ int wrap_slot(int64_t v, int K) {
   int s = (int)(v % K);
@@ -251,7 +279,7 @@ __device__ __forceinline__ int wrap_slot(int64_t v, int K) {
 // p pairs with slot (frame - p) mod K).
 // ---------------------------------------------------------------------------
 template <typename HT, int G, bool NT>
-__device__ void mac_item(int Qn, const DevTier& T, const Item& it,
+__device__ __forceinline__ void mac_item(int Qn, const DevTier& T, const Item& it,
                          const Group& grp, int64_t frame, float2* red) {
   constexpr int C = HVec<HT>::C;
   const int P = T.P;
@@ -391,18 +419,18 @@ __device__ __forceinline__ TwRegs load_twiddles_regs(const DevTier& T) {
   TwRegs r;
   r.n = tw_lds_len(T.P);
   if (r.n > kTwRegs * kThreads) r.n = 0;  // too long: stage_twiddles instead
+  // unconditional loads at clamped indices (a load under a lane-divergent
+  // guard makes the wave wait for every load in flight)
 #pragma unroll
-  for (int i = 0; i < kTwRegs; ++i) {
-    const int j = threadIdx.x + i * kThreads;
-    if (j < r.n) r.v[i] = T.tw[j];
-  }
+  for (int i = 0; i < kTwRegs; ++i)
+    if (i * kThreads < r.n) r.v[i] = T.tw[min((int)threadIdx.x + i * kThreads, r.n - 1)];
   return r;
 }
 __device__ __forceinline__ void store_twiddles_regs(const TwRegs& r, float2* dst) {
 #pragma unroll
   for (int i = 0; i < kTwRegs; ++i) {
     const int j = threadIdx.x + i * kThreads;
-    if (j < r.n) dst[j] = r.v[i];
+    if (j < r.n) dst[j] = pin(r.v[i]);
   }
 }
 
@@ -425,7 +453,7 @@ __device__ __forceinline__ const float2* stage_twiddles(const DevTier& T, float2
 // nslot, so results are reproducible).  Y: [G][P] in LDS; scratch:
 // red_scratch(E) float2.  Ends with a barrier.
 template <typename HT, int G>
-__device__ void head_reduce(const KArgs& A, const DevTier& T, const Group& grp, int64_t n,
+__device__ __forceinline__ void head_reduce(const KArgs& A, const DevTier& T, const Group& grp, int64_t n,
                             float2* Y, float2* scratch) {
   const int P = T.P;
   const int E = grp.nl * P;
@@ -478,6 +506,105 @@ __device__ void head_reduce(const KArgs& A, const DevTier& T, const Group& grp, 
   __syncthreads();
 }
 
+// The same reduction split in two, so that its global round trip overlaps
+// the head's transform of the block's window (which does not depend on it):
+// red_issue() requests every value one thread adds -- its run of partial
+// slots of its one element and the operands of its share of the p = 1 term
+// -- into registers, red_finish() adds them into Y after the transform.
+// Only for element counts E that are powers of two up to 256 (one element
+// per thread, red_span(E) = E) and per-thread shares within the register
+// budget (red_fits); other shapes take head_reduce().
+template <typename HT>
+struct HeadRed {
+  static constexpr int kSlots = 16, kInputs = 4;
+  float2 s[kSlots];
+  typename HVec<HT>::one_t h1[kInputs];
+  float2 x1[kInputs];
+};
+__device__ __forceinline__ bool red_fits(int E, int nslot, int Q, int HRslots, int HRinputs) {
+  if (E > kThreads || (E & (E - 1)) != 0) return false;
+  const int ng = kThreads / E;
+  return (nslot + ng - 1) / ng <= HRslots && (Q + ng - 1) / ng <= HRinputs;
+}
+template <typename HT, int G>
+__device__ __forceinline__ void red_issue(const KArgs& A, const DevTier& T, const Group& grp,
+                                          int64_t n, HeadRed<HT>& r, bool on) {
+  const int P = T.P;
+  const int E = grp.nl * P;
+  const int64_t stride = (int64_t)G * P;
+  const float2* base = T.partial + (int64_t)grp.slot0 * stride;
+  const int tid = threadIdx.x;
+  const int ng = kThreads / E, tg = tid / E, e = tid % E;
+  const int per = (grp.nslot + ng - 1) / ng;
+  const int s0 = min(grp.nslot, tg * per);
+  // Always kSlots loads, at clamped indices (a valid dummy address when the
+  // group has no slots, or when the reduction is not split: on = false),
+  // with no guard: the compiler then knows that at least kSlots loads follow
+  // the window's and waits for the window alone (with a guarded or variable
+  // count it waits for every load in flight).  red_finish adds only the
+  // thread's own slots.
+  const bool any = on && grp.nslot > 0;
+  const float2* src = any ? base + e : T.tw;
+  const int64_t step = any ? stride : 0;
+  const int last = max(grp.nslot - 1, 0);
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int i = 0; i < HeadRed<HT>::kSlots; ++i) r.s[i] = src[min(s0 + i, last) * step];
+  if (!on || T.K < 2) return;
+  const int slot1 = wrap_slot(n - 1, T.K);
+  const HT* H01 = reinterpret_cast<const HT*>(A.H01);
+  const int g = e / P, k = e - g * P;
+  const int l = grp.l0 + g;
+  const int nq = (A.Q + ng - 1) / ng;
+#pragma unroll
+  for (int j = 0; j < HeadRed<HT>::kInputs; ++j) {
+    if (j < nq) {
+      const int q = min(tg + j * ng, A.Q - 1);
+      r.h1[j] = HVec<HT>::load1_raw(H01 + ((int64_t)(l * A.Q + q) * 2 + 1) * P + k);
+      r.x1[j] = T.X[((int64_t)q * T.K + slot1) * P + k];
+    }
+  }
+}
+// Y [E] in LDS; scratch: kThreads float2.  Every thread's element is its own
+// (e = tid for tid < E) when this returns; no barrier after the last write.
+template <typename HT, int G>
+__device__ __forceinline__ void red_finish(const KArgs& A, const DevTier& T, const Group& grp,
+                                           const HeadRed<HT>& r, float2* Y, float2* scratch) {
+  const int P = T.P;
+  const int E = grp.nl * P;
+  const int tid = threadIdx.x;
+  const int ng = kThreads / E, tg = tid / E, e = tid % E;
+  const int per = (grp.nslot + ng - 1) / ng;
+  const int s0 = min(grp.nslot, tg * per), s1 = min(grp.nslot, s0 + per);
+  const int k = e % P;
+  float2 acc = make_float2(0.f, 0.f);
+  if (T.K >= 2) {
+    const int nq = (A.Q + ng - 1) / ng;
+#pragma unroll
+    for (int j = 0; j < HeadRed<HT>::kInputs; ++j) {
+      if (j < nq && tg + j * ng < A.Q) {
+        const float2 h1 = HVec<HT>::cvt1(pin(r.h1[j]));
+        const float2 x1 = pin(r.x1[j]);
+        acc = cadd(acc, (k == 0) ? make_float2(h1.x * x1.x, h1.y * x1.y) : cmul(h1, x1));
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < HeadRed<HT>::kSlots; ++i)
+    if (i < per && s0 + i < s1) acc = cadd(acc, pin(r.s[i]));
+  if (ng == 1) {
+    Y[e] = acc;
+    return;
+  }
+  scratch[tg * E + e] = acc;
+  __syncthreads();
+  if (tid < E) {
+    float2 t = scratch[tid];
+    for (int g2 = 1; g2 < ng; ++g2) t = cadd(t, scratch[g2 * E + tid]);
+    Y[tid] = t;
+  }
+}
+
 // Fused feedback: thread 0 waits until every feedback head of this launch
 // has published c_{n-1} (they are dispatched first and wait for nothing),
 // then the workgroup proceeds.  The spin is bounded all the same; a wait that
@@ -522,7 +649,7 @@ __host__ __device__ inline HeadLds head_lds(int P, int G, int nq) {
 // of the partial-sum reduction, the critical path under the tails' streaming,
 // independent of G.
 template <typename HT, int G>
-__device__ void head_work(const KArgs& A, int64_t n, const Group& grp, int gsel, float2* lds) {
+__device__ __forceinline__ void head_work(const KArgs& A, int64_t n, const Group& grp, int gsel, float2* lds) {
   const int tid = threadIdx.x;
   const DevTier& T = A.tier[0];
   // P bins per row, half the window of 2P samples: P = B (n_f = 2B), or
@@ -561,60 +688,72 @@ __device__ void head_work(const KArgs& A, int64_t n, const Group& grp, int gsel,
   const bool pre_w = nb0 * P <= WMAX * kThreads && !A.fc_on;
   const bool pre_h = ept * nb0 <= HMAX;
   const bool pre_r = A.n_tiers - 1 <= TMAX && eo <= RMAX * kThreads;
-  // feedback estimate sample i of input q (fused: written in this launch by
-  // another workgroup, so read where every XCD sees it)
-  auto sub_at = [&](int q, int i) {
-    const float* p = A.sub + (int64_t)q * A.B + i;
-    return A.fc_on ? __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) : *p;
+  // Window sample pair m of input q, [w_2m, w_2m+1]: both from the history
+  // (2m < cur) or both from this block's input (cur is even).  The source is
+  // selected per lane and read with unconditional loads (clamped indices,
+  // guards applied where the values are used): a load under a lane-divergent
+  // branch makes the wave wait for every load in flight, which would undo
+  // the prefetch.
+  struct WinRaw {
+    float2 w, s;  // samples; the feedback estimate of input samples
+    int live;
   };
-  auto window = [&](int e, int q0) {
+  auto win_load = [&](int e, int q0) {
     const int b = e / P, m = e - b * P;
     const int q = q0 + b;
-    const float* hq = A.hist + (int64_t)q * (A.hist_mask + 1);
-    const float* iq = A.in + (int64_t)q * A.B;
-    const int i0 = 2 * m, i1 = 2 * m + 1;
-    float w0, w1;
-    if (A.sub == nullptr) {
-      w0 = i0 < cur ? hq[(wh0 + i0) & A.hist_mask] : iq[i0 - cur];
-      w1 = i1 < cur ? hq[(wh0 + i1) & A.hist_mask] : iq[i1 - cur];
-    } else {  // microphone minus the previous block's feedback estimate
-      w0 = i0 < cur ? hq[(wh0 + i0) & A.hist_mask] : iq[i0 - cur] - sub_at(q, i0 - cur);
-      w1 = i1 < cur ? hq[(wh0 + i1) & A.hist_mask] : iq[i1 - cur] - sub_at(q, i1 - cur);
+    const int i0 = 2 * m;
+    const float* p = i0 < cur ? A.hist + (int64_t)q * (A.hist_mask + 1) + ((wh0 + i0) & A.hist_mask)
+                              : A.in + (int64_t)q * A.B + (i0 - cur);
+    WinRaw r;
+    r.w = make_float2(p[0], p[1]);
+    r.s = make_float2(0.f, 0.f);
+    if (A.sub != nullptr) {  // microphone minus the previous block's feedback estimate
+      const float* ps = A.sub + (int64_t)q * A.B + max(i0 - cur, 0);
+      // (fused: written in this launch by another workgroup, so read where
+      // every XCD sees it)
+      r.s = A.fc_on ? make_float2(__hip_atomic_load(ps, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM),
+                                  __hip_atomic_load(ps + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM))
+                    : make_float2(ps[0], ps[1]);
     }
-    if (A.live != nullptr && A.live[q] == 0) {  // a select, so NaN input stays out
-      if (i0 >= cur) w0 = 0.f;
-      if (i1 >= cur) w1 = 0.f;
-    }
-    return make_float2(w0, w1);
+    r.live = A.live != nullptr ? A.live[q] : 1;
+    return r;
+  };
+  auto win_value = [&](int e, const WinRaw& r) {
+    if (2 * (e % P) < cur) return r.w;
+    const float2 v = make_float2(r.w.x - r.s.x, r.w.y - r.s.y);
+    return r.live == 0 ? make_float2(0.f, 0.f) : v;  // a select: NaN input stays out
   };
   auto h0_at = [&](int e, int q) {
     const int g = e / P, k = e - g * P;
     return HVec<HT>::load1(H01 + ((int64_t)((grp.l0 + g) * A.Q + q) * 2) * P + k);
   };
-  float2 wv[WMAX], hv[HMAX];
+  WinRaw wv[WMAX];
+  typename HVec<HT>::one_t hv[HMAX];
   float rv[RMAX][TMAX][2];
   if (pre_w) {
 #pragma unroll
-    for (int i = 0; i < WMAX; ++i) {
-      const int e = tid + i * kThreads;
-      if (e < nb0 * P) wv[i] = window(e, 0);
-    }
+    for (int i = 0; i < WMAX; ++i)
+      if (i * kThreads < nb0 * P) wv[i] = win_load(min(tid + i * kThreads, nb0 * P - 1), 0);
   }
+  __builtin_amdgcn_sched_barrier(0);  // the window's loads go out first
   if (pre_h) {
 #pragma unroll
     for (int i = 0; i < HMAX; ++i) {
       const int ie = i / nb0, b = i - ie * nb0;
-      const int e = tid + ie * kThreads;
-      if (ie < ept && e < E) hv[i] = h0_at(e, b);
+      if (ie < ept) {
+        const int e = min(tid + ie * kThreads, E - 1);
+        const int g = e / P, k = e - g * P;
+        hv[i] = HVec<HT>::load1_raw(H01 + ((int64_t)((grp.l0 + g) * A.Q + b) * 2) * P + k);
+      }
     }
   }
   if (pre_r) {
 #pragma unroll
     for (int i = 0; i < RMAX; ++i) {
-      const int e = tid + i * kThreads;
+      const int e = min(tid + i * kThreads, eo - 1);
 #pragma unroll
       for (int t = 0; t < TMAX; ++t) {
-        if (e < eo && t + 1 < A.n_tiers) {
+        if (i * kThreads < eo && t + 1 < A.n_tiers) {
           const int g = e / hb, j = 2 * (e - g * hb);
           const float* ring = A.tier[t + 1].oring + (int64_t)(grp.l0 + g) * (A.ring_mask + 1);
           rv[i][t][0] = ring[(n * A.B + j) & A.ring_mask];
@@ -625,13 +764,24 @@ __device__ void head_work(const KArgs& A, int64_t n, const Group& grp, int gsel,
   }
 
   // 1. the terms p >= 2, summed by the previous launch's tail items, and the
-  //    term p = 1 (ring slot n-1)
+  //    term p = 1 (ring slot n-1): requested now and added up after the
+  //    window's transform (step 2) where the shape allows, else done here
   const DevTier Tcur = [&] {
     DevTier t = T;
     t.partial = T.partial + (n & 1) * (int64_t)T.nslots * G * P + (int64_t)gsel * P;
     return t;
   }();
-  head_reduce<HT, G>(A, Tcur, grp, n, Y, scratch);
+  HeadRed<HT> red;
+  const bool split = red_fits(E, grp.nslot, A.Q, HeadRed<HT>::kSlots, HeadRed<HT>::kInputs);
+  // (issued on both paths: one straight-line sequence of loads after the
+  // window's, whatever the shape)
+  red_issue<HT, G>(A, Tcur, grp, n, red, split);
+  if (!split) {
+    head_reduce<HT, G>(A, Tcur, grp, n, Y, scratch);
+    // nothing left in flight on this path, so that the compiler's count of
+    // loads still outstanding where the paths meet is the split path's
+    __builtin_amdgcn_s_waitcnt(0);
+  }
   store_twiddles_regs(twr, lds + L.tw);
 
   // fused feedback: wait until every feedback head of this launch has
@@ -640,35 +790,35 @@ __device__ void head_work(const KArgs& A, int64_t n, const Group& grp, int gsel,
 
   // 2. the term p = 0: window -> real FFT -> ring slot n mod K, times H_{l,q,0}
   const int slot0 = wrap_slot(n, T.K);
-  for (int q0 = 0; q0 < A.Q; q0 += A.head_nq) {
-    const int nb = min(A.head_nq, A.Q - q0);
-    if (q0 == 0 && pre_w) {
-#pragma unroll
-      for (int i = 0; i < WMAX; ++i) {
-        const int e = tid + i * kThreads;
-        if (e < nb * P) Xa[e] = wv[i];
-      }
-    } else {
-      for (int e = tid; e < nb * P; e += kThreads) Xa[e] = window(e, q0);
+  // window sample pair e of inputs q0, q0 + 1, ... into LDS; the first group
+  // also stores the block's input samples (as windowed: feedback estimate
+  // subtracted, silent inputs zero) into the history for later launches
+  auto put = [&](int q0, int e, float2 v) {
+    Xa[e] = v;
+    const int bq = e / P, i = 2 * (e - bq * P) - cur;
+    if (grp.l0 == 0 && i >= 0) {
+      float* h = A.hist + (int64_t)(q0 + bq) * (A.hist_mask + 1);
+      h[(n * A.B + i) & A.hist_mask] = v.x;
+      h[(n * A.B + i + 1) & A.hist_mask] = v.y;
     }
+  };
+  // the windows of nb inputs from q0 in LDS -> real FFT -> ring slot n mod
+  // K; the term p = 0 added into Y (first: the chunk the prefetch covered,
+  // which also adds up the split reduction first)
+  auto chunk = [&](int q0, int nb, bool first) {
     __syncthreads();
     float2* z = fft_any<false>(Xa, Xb, P, logP, T.r3, tw, nb);
     float2* x = (z == Xa) ? Xb : Xa;
     rfft_post(z, x, P, tw + P, nb);
-    if (grp.l0 == 0) {  // the first group stores the block for later launches
+    if (grp.l0 == 0) {  // the first group stores the block's spectrum for later launches
       for (int e = tid; e < nb * P; e += kThreads) {
         const int b = e / P, k = e - b * P;
         T.X[((int64_t)(q0 + b) * T.K + slot0) * P + k] = x[e];
       }
-      for (int e = tid; e < nb * A.B; e += kThreads) {
-        const int b = e / A.B, i = e - b * A.B;
-        const int q = q0 + b;
-        const float v = A.in[(int64_t)q * A.B + i] - (A.sub ? sub_at(q, i) : 0.f);
-        A.hist[(int64_t)q * (A.hist_mask + 1) + ((n * A.B + i) & A.hist_mask)] =
-            (A.live != nullptr && A.live[q] == 0) ? 0.f : v;
-      }
     }
-    if (q0 == 0 && pre_h) {
+    // the reduction's registers into Y (element e = tid, as below)
+    if (first && split) red_finish<HT, G>(A, Tcur, grp, red, Y, scratch);
+    if (first && pre_h) {
       // register slot i holds element ie = i / nb, input b = i % nb (the
       // same mapping as the prefetch); each element belongs to this thread
 #pragma unroll
@@ -677,7 +827,7 @@ __device__ void head_work(const KArgs& A, int64_t n, const Group& grp, int gsel,
         const int e = tid + ie * kThreads;
         if (ie >= ept || e >= E) continue;
         const int k = e % P;
-        const float2 h0 = hv[i];
+        const float2 h0 = HVec<HT>::cvt1(pin(hv[i]));
         const float2 x0 = x[b * P + k];
         Y[e] = cadd(Y[e], (k == 0) ? make_float2(h0.x * x0.x, h0.y * x0.y) : cmul(h0, x0));
       }
@@ -695,6 +845,29 @@ __device__ void head_work(const KArgs& A, int64_t n, const Group& grp, int gsel,
       }
     }
     __syncthreads();
+  };
+  // first chunk, from the prefetched registers where it was prefetched (kept
+  // out of the loop below: the compiler then waits for these loads alone)
+  if (pre_w) {
+#pragma unroll
+    for (int i = 0; i < WMAX; ++i) {
+      const int e = tid + i * kThreads;
+      if (e < nb0 * P) {
+        WinRaw r = wv[i];
+        r.w = pin(r.w);
+        r.s = pin(r.s);
+        r.live = pin(r.live);
+        put(0, e, win_value(e, r));
+      }
+    }
+  } else {
+    for (int e = tid; e < nb0 * P; e += kThreads) put(0, e, win_value(e, win_load(e, 0)));
+  }
+  chunk(0, nb0, true);
+  for (int q0 = A.head_nq; q0 < A.Q; q0 += A.head_nq) {
+    const int nb = min(A.head_nq, A.Q - q0);
+    for (int e = tid; e < nb * P; e += kThreads) put(q0, e, win_value(e, win_load(e, q0)));
+    chunk(q0, nb, false);
   }
 
   // n_f = 3B (Sec. V): this output's accumulated spectrum is the spectrum
@@ -747,8 +920,8 @@ __device__ void head_work(const KArgs& A, int64_t n, const Group& grp, int gsel,
 #pragma unroll
       for (int t = 0; t < TMAX; ++t) {
         if (t + 1 < A.n_tiers) {
-          y0 += rv[i][t][0];
-          y1 += rv[i][t][1];
+          y0 += pin(rv[i][t][0]);
+          y1 += pin(rv[i][t][1]);
         }
       }
       emit(e, y0, y1);
@@ -821,7 +994,7 @@ __device__ void head_work(const KArgs& A, int64_t n, const Group& grp, int gsel,
 // of the 2B samples; then it counts itself done (system scope, after making
 // c visible).  Y' are the synthesis heads' transforms of their outputs.
 template <typename HT, int G>
-__device__ void fc_head_work(const KArgs& A, int64_t n, int j, float2* lds) {
+__device__ __forceinline__ void fc_head_work(const KArgs& A, int64_t n, int j, float2* lds) {
   const FcArgs& F = A.fc;
   const DevTier& T = F.T;
   const int P = T.P, logP = T.logP, tid = threadIdx.x;
@@ -968,7 +1141,7 @@ __device__ __forceinline__ float block_sample(const KArgs& A, int q, int i) {
 }
 
 template <int G>
-__device__ void tier_fft_a(const KArgs& A, int64_t n, const Item& it, float2* lds) {
+__device__ __forceinline__ void tier_fft_a(const KArgs& A, int64_t n, const Item& it, float2* lds) {
   const DevTier& T = A.tier[it.tier];
   const int tid = threadIdx.x, P = T.P;
   const int lg1 = T.lg1, N1 = 1 << lg1, lg2 = T.logP - lg1, N2 = 1 << lg2;
@@ -1002,7 +1175,7 @@ __device__ void tier_fft_a(const KArgs& A, int64_t n, const Item& it, float2* ld
 }
 
 template <int G>
-__device__ void tier_fft_b(const KArgs& A, int64_t n, const Item& it, float2* lds) {
+__device__ __forceinline__ void tier_fft_b(const KArgs& A, int64_t n, const Item& it, float2* lds) {
   const DevTier& T = A.tier[it.tier];
   const int tid = threadIdx.x, P = T.P;
   const int lg1 = T.lg1, N1 = 1 << lg1, lg2 = T.logP - lg1, N2 = 1 << lg2;
@@ -1043,7 +1216,7 @@ __device__ void tier_fft_b(const KArgs& A, int64_t n, const Item& it, float2* ld
 }
 
 template <int G>
-__device__ void tier_fin_a(const KArgs& A, int64_t n, const Item& it, float2* lds) {
+__device__ __forceinline__ void tier_fin_a(const KArgs& A, int64_t n, const Item& it, float2* lds) {
   const DevTier& T = A.tier[it.tier];
   const int tid = threadIdx.x, P = T.P;
   const int lg1 = T.lg1, N1 = 1 << lg1, lg2 = T.logP - lg1, N2 = 1 << lg2;
@@ -1099,7 +1272,7 @@ __device__ void tier_fin_a(const KArgs& A, int64_t n, const Item& it, float2* ld
 }
 
 template <int G>
-__device__ void tier_fin_b(const KArgs& A, int64_t n, const Item& it, float2* lds) {
+__device__ __forceinline__ void tier_fin_b(const KArgs& A, int64_t n, const Item& it, float2* lds) {
   const DevTier& T = A.tier[it.tier];
   const int tid = threadIdx.x, P = T.P;
   const int lg1 = T.lg1, lg2 = T.logP - lg1, N2 = 1 << lg2;
@@ -1130,7 +1303,7 @@ __device__ void tier_fin_b(const KArgs& A, int64_t n, const Item& it, float2* ld
 }
 
 template <int G>
-__device__ void tier_pass(const KArgs& A, int64_t n, const Item& it, float2* lds) {
+__device__ __forceinline__ void tier_pass(const KArgs& A, int64_t n, const Item& it, float2* lds) {
   switch (it.kind) {
     case K_FFT_A: tier_fft_a<G>(A, n, it, lds); break;
     case K_FFT_B: tier_fft_b<G>(A, n, it, lds); break;

@@ -1528,24 +1528,31 @@ namespace {
 std::vector<std::vector<std::pair<int, int>>> scheme_candidates(int B, int64_t max_len) {
   std::vector<std::vector<std::pair<int, int>>> out;
   out.push_back({{B, 0}});
-  for (int ratio : {8, 4}) {
-    std::vector<std::pair<int, int>> sch;
-    int64_t o = 0;
-    int64_t P = B;
-    while (true) {
-      const int64_t Pn = P * ratio;
-      // start of the next tier: 2 P - B gives it P / B blocks of slack; at
-      // least P + 4 B
-      const int64_t on = std::max<int64_t>(2 * Pn - B, Pn + 4 * (int64_t)B);
-      if (Pn > 8192 || max_len <= on) break;
-      sch.push_back({(int)P, (int)((on - o) / P)});
-      o = on;
-      P = Pn;
-    }
-    if (sch.empty()) continue;
-    sch.push_back({(int)P, 0});
-    if (std::find(out.begin(), out.end(), sch) == out.end()) out.push_back(sch);
-  }
+  // partition ratio between tiers, largest partition, and how many times
+  // its minimum length the first (block-sized) tier covers
+  for (int ratio : {8, 4})
+    for (int64_t cap : {8192, 2048})
+      for (int first : {1, 2}) {
+        std::vector<std::pair<int, int>> sch;
+        int64_t o = 0;
+        int64_t P = B;
+        while (true) {
+          const int64_t Pn = P * ratio;
+          // a tier starts at least 2 P - B in (P / B blocks of slack) and at
+          // least P + 4 B; counts are whole partitions
+          int64_t on = std::max<int64_t>(2 * Pn - B, Pn + 4 * (int64_t)B);
+          if (sch.empty()) on *= first;
+          const int64_t count = (on - o + P - 1) / P;
+          on = o + count * P;
+          if (Pn > cap || max_len <= on) break;
+          sch.push_back({(int)P, (int)count});
+          o = on;
+          P = Pn;
+        }
+        if (sch.empty()) continue;
+        sch.push_back({(int)P, 0});
+        if (std::find(out.begin(), out.end(), sch) == out.end()) out.push_back(sch);
+      }
   return out;
 }
 
@@ -1941,7 +1948,9 @@ std::string tuning_key(double fs, int32_t block, const rta_scheme* scheme, int32
       h *= 1099511628211ull;
     }
   }
-  std::string sch = "auto";
+  // "auto" names the candidate set of scheme_candidates(): a changed set
+  // gets a new name so that older entries miss
+  std::string sch = "auto2";
   if (scheme != nullptr) {
     sch.clear();
     for (int t = 0; t < scheme->n_tiers; ++t)

@@ -179,7 +179,7 @@ def test_tuning_cache_hit_needs_no_device(rta, tmp_path):
     lens = [4000, 2500]
     filt = [[np.zeros(n, np.float32) for n in lens]]
     key = (f"unknown;cu=0;fs={format(48000.0, '.17g')};B=64;Q=1;L=2;"
-           f"len={_fnv1a64(lens):016x};spectra=0;flags=0;blocks=8;scheme=auto")
+           f"len={_fnv1a64(lens):016x};spectra=0;flags=0;blocks=8;scheme=auto2")
     path = tmp_path / "tuning.jsonl"
     path.write_text(
         '{"key": "other", "outputs_per_group": 4, "tail_items": 0, "tail_rows": 0, '
