@@ -141,6 +141,15 @@ typedef struct rta_info {
     int64_t host_slowest_call;
     double  host_slowest_us;
     int64_t host_late_waits;
+    int32_t bin_slices;           /* first-tier items per partition row,
+                                     each over 1/bin_slices of the bins:
+                                     rta_tuning's, or chosen when a long
+                                     filter feeds few outputs (the partial
+                                     slots per output group are capped so
+                                     that a head adds them up while it
+                                     transforms its window)                */
+    int32_t max_group_slots;      /* the most partial slots one output
+                                     group's head adds up per block        */
 } rta_info;
 
 /* Create a context.

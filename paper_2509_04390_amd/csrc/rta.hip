@@ -125,9 +125,10 @@ struct rta_ctx {
   TierHost tier[kMaxTiers];
   int G = 1, rows_per_item = 0, n_phase = 1, max_items = 0, n_items = 0;
   int tail_items = 512, tier_rows = 16;
+  int max_group_slots = 0;     // first tier: the most partial slots of one output group
   int spectra_loads = 0;       // 0 default, 1 non-temporal, 2 ordinary
   bool nt = true;              // non-temporal spectra loads
-  int bin_slices = 1;          // first-tier bin slices per partition row
+  int bin_slices = 0;          // first-tier bin slices per partition row (0: chosen by the plan)
   int n_groups = 0, head_slots = 0, head_nq = 1;
   int64_t hist_len = 0, ring_len = 0;
   size_t lds = 0;              // k_block dynamic LDS
@@ -505,7 +506,7 @@ int build_plan(rta_ctx* c, Plan& plan) {
     // 64 / (W / C) rows
     // (a power of two dividing P: with n_f = 3B, P = 3B/2 gives thirds)
     const int Wmax = std::min(T.r3 ? T.P / 3 : T.P, kThreads * C);
-    const int W = std::max(C, Wmax / std::max(1, c->bin_slices)), nslice = T.P / W;
+    int W = std::max(C, Wmax / std::max(1, c->bin_slices)), nslice = T.P / W;
     int64_t total_rows = 0;
     for (const Group& gr : plan.groups)
       for (int q = 0; q < c->Q; ++q) total_rows += std::max(0, group_rows(T, gr, q) - 2);
@@ -517,6 +518,43 @@ int build_plan(rta_ctx* c, Plan& plan) {
     if (R <= 0) {
       const int64_t target_items = std::max(1, c->tail_items);
       R = (int)std::max<int64_t>(8, (total_rows * nslice + target_items - 1) / target_items);
+      // Slots per output group within what a head adds up from registers
+      // while it transforms its window (HeadRed: 16 slots per thread, 256 / P
+      // threads per bin): with few outputs and long filters the item count
+      // above would give one group hundreds of slots, and its head would
+      // reduce them after the transform.  Rows per item grow to the cap; with
+      // automatic slices, narrower bin ranges then cut the items back to
+      // about 32 KB of rows each (one workgroup streams some 10-15 GB/s, so
+      // an item's share stays within a few microseconds).
+      int Rmin = 8;
+      const int ng = T.P <= kThreads ? kThreads / T.P : 0;
+      if (!fixed && !T.r3 && ng > 0 && is_pow2(T.P) &&
+          (c->Q + ng - 1) / ng <= HeadRed<float2>::kInputs) {
+        const int cap = HeadRed<float2>::kSlots * ng;
+        auto ranges = [&](int r, bool worst) {  // slots of the fullest group, or all ranges
+          int64_t tot = 0, m = 0;
+          for (const Group& gr : plan.groups) {
+            int64_t ns = 0;
+            for (int q = 0; q < c->Q; ++q) ns += (std::max(0, group_rows(T, gr, q) - 2) + r - 1) / r;
+            tot += ns;
+            m = std::max(m, ns);
+          }
+          return worst ? m : tot;
+        };
+        if (ranges(R, true) > cap) {
+          int rc = R;
+          while (ranges(rc, true) > cap) rc = std::max(rc + 1, rc + rc / 16);
+          while (rc > R && ranges(rc - 1, true) <= cap) --rc;  // the smallest that fits
+          if (c->bin_slices == 0)
+            while (ranges(rc, false) * nslice < target_items && W / 2 >= C && T.P % (W / 2) == 0 &&
+                   total_rows * T.P * 8 / (ranges(rc, false) * nslice) > (32 << 10)) {
+              W /= 2;
+              nslice *= 2;
+            }
+          R = (int)std::max<int64_t>(rc, (total_rows * nslice + target_items - 1) / target_items);
+          Rmin = rc;
+        }
+      }
       // XCD balance: the partition ranges of one input form one bucket per
       // range (all groups, all slices), spread over the 8 XCDs; make the
       // number of ranges of the longest (group, input) times the inputs a
@@ -529,13 +567,14 @@ int build_plan(rta_ctx* c, Plan& plan) {
       int step = kXcds;
       for (int qq = c->Q; qq % 2 == 0 && step > 1; qq /= 2) step /= 2;  // 8 / gcd(Q, 8)
       if ((kmax + R - 1) / R >= kXcds)  // the largest R' <= R giving a multiple of step
-        for (int r2 = R; r2 >= 8; --r2)
+        for (int r2 = R; r2 >= Rmin; --r2)
           if (((kmax + r2 - 1) / r2) % step == 0) {
             R = r2;
             break;
           }
     }
     c->rows_per_item = R;
+    if (c->bin_slices == 0) c->bin_slices = Wmax / W;  // later plans keep this layout
     const int nch_cap = (cap_rows + R - 1) / R;
     int slot = 0;
     for (int g = 0; g < ngroups; ++g) {
@@ -576,6 +615,8 @@ int build_plan(rta_ctx* c, Plan& plan) {
       }
     }
     T.nslots = slot;
+    c->max_group_slots = 0;
+    for (const Group& gr : plan.groups) c->max_group_slots = std::max(c->max_group_slots, gr.nslot);
   }
 
   // ---- later tiers
@@ -2269,6 +2310,8 @@ int rta_query(rta_ctx* c, rta_info* info) {
   info->host_slowest_call = c->hs.slowest_call;
   info->host_slowest_us = c->hs.slowest_us;
   info->host_late_waits = c->hs.late;
+  info->bin_slices = std::max(1, c->bin_slices);
+  info->max_group_slots = c->max_group_slots;
   return c->poisoned ? RTA_E_DEVICE : RTA_OK;
 }
 

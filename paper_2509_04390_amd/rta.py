@@ -90,7 +90,9 @@ class rta_info(ctypes.Structure):
                 ("host_sum_us", ctypes.c_double * 4),
                 ("host_slowest_call", ctypes.c_int64),
                 ("host_slowest_us", ctypes.c_double),
-                ("host_late_waits", ctypes.c_int64)]
+                ("host_late_waits", ctypes.c_int64),
+                ("bin_slices", ctypes.c_int32),
+                ("max_group_slots", ctypes.c_int32)]
 
 
 class rta_tuning(ctypes.Structure):

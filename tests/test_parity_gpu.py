@@ -207,6 +207,31 @@ def test_small_config_fp32_streamed_and_tail(rta):
     check_db(y[:, idx], refd, FP32_DB, "small/direct")
 
 
+@pytest.mark.parametrize("B,L,taps", [(128, 1, 200_000), (128, 4, 60_000), (256, 1, 65_536),
+                                         (64, 2, 40_000)])
+def test_few_outputs_long_filters_slot_capped_plan(rta, B, L, taps):
+    """Few outputs and long filters: the default plan caps the partial slots of
+    an output group at what a head adds up from registers (16 per thread,
+    256 / P threads per bin) and slices the rows' bins to keep items small.
+    The caps and the output against the oracle, sample by sample."""
+    lens = [[taps] * L]
+    filt = make_filters(B + L, lens)
+    n = -(-(taps + 4 * B) // B) * B  # past the filter length: every partition live
+    x = workloads.white_noise(B + L + 7, 1, n)
+    with rta.Convolver(filt, B) as cv:
+        info = cv.info()
+        y = cv.run_device(x)
+    P = B  # n_f = 2B: P bins per row
+    cap = 16 * (256 // P)
+    say(f"B={B} L={L} taps={taps}: rows/item {info['rows_per_item']}, bin slices "
+        f"{info['bin_slices']}, slots per group {info['max_group_slots']} (cap {cap}), grid {info['grid']}")
+    assert 0 < info["max_group_slots"] <= cap
+    rng = np.random.default_rng(B + L)
+    idx = np.unique(np.r_[0, B - 1, B, 2 * B, taps - 1, taps, n - B, n - 1, rng.integers(0, n, 300)])
+    ref = oracle.direct_at(x, filt, idx)
+    check_db(y[:, idx], ref, FP32_DB, f"B={B} L={L}")
+
+
 def test_main_config_full_size_sampled(rta):
     """1 input -> 32 outputs, 480,000-tap filters, block 128, 2,000 blocks."""
     wl = workloads.config("main")
