@@ -60,7 +60,7 @@ enum ItemKind : int32_t {
   K_FIN_B = 5   // N2-point inverse transforms of rows -> output ring
 };
 
-struct Item {          // one workgroup's work in one block (48 bytes)
+struct Item {          // one workgroup's work in one block (96 bytes)
   int32_t kind;        // ItemKind
   int32_t w;           // K_MAC: bins of the slice (divides P; W/C lanes per row);
                        // tier passes: columns (rows) or column pairs per item
@@ -74,8 +74,15 @@ struct Item {          // one workgroup's work in one block (48 bytes)
   int32_t acc;         // K_MAC of a later tier: add to the slot (0: store)
   int32_t lag;         // tiers >= 1: launch index minus the block in which
                        // the frame's input completed
-  int32_t pad;
+  int32_t nl;          // K_MAC: outputs of its group
+  // K_MAC, per output g of the group: the end of the partitions to read,
+  // min(p1, partitions of pair (l0 + g, q)) (0: no path), and that pair's
+  // first spectrum row.  Carried here so that a tail workgroup needs one
+  // load (its item) before it streams, not a chain of table lookups.
+  int32_t pend[4];
+  int64_t row[4];
 };
+static_assert(sizeof(Item) == 96, "Item layout");
 
 struct Group {         // outputs reduced together (16 bytes)
   int32_t l0, nl;      // first output, outputs in the group (<= G)
@@ -279,8 +286,7 @@ __device__ __forceinline__ int wrap_slot(int64_t v, int K) {
 // p pairs with slot (frame - p) mod K).
 // ---------------------------------------------------------------------------
 template <typename HT, int G, bool NT>
-__device__ __forceinline__ void mac_item(int Qn, const DevTier& T, const Item& it,
-                         const Group& grp, int64_t frame, float2* red) {
+__device__ __forceinline__ void mac_item(const DevTier& T, const Item& it, int64_t frame, float2* red) {
   constexpr int C = HVec<HT>::C;
   const int P = T.P;
   const int W = it.w;                                  // bins per item slice
@@ -296,16 +302,9 @@ __device__ __forceinline__ void mac_item(int Qn, const DevTier& T, const Item& i
   int pend[G];
 #pragma unroll
   for (int g = 0; g < G; ++g) {
-    pend[g] = 0;
-    hb[g] = Hbase;
-    if (g < grp.nl) {
-      const int pair = (grp.l0 + g) * Qn + q;
-      const int64_t row = T.pair_row[pair];
-      if (row >= 0) {
-        pend[g] = min(it.p1, T.pair_K[pair]);
-        hb[g] = Hbase + row * (int64_t)P + kb;
-      }
-    }
+    const bool on = g < it.nl;
+    pend[g] = on ? it.pend[g] : 0;
+    hb[g] = Hbase + (on ? it.row[g] : 0) * (int64_t)P + kb;
   }
 
   float acc[G][C][4];
@@ -1369,10 +1368,11 @@ __global__ __launch_bounds__(kThreads) void k_block(const KArgs A) {
     if (it.kind == K_NOP) return;
     DevTier T = A.fc.T;
     T.partial += (n & 1) * (int64_t)T.nslots * G * T.P;
-    mac_item<HT, G, NT>(A.fc.Qf, T, it, A.fc.groups[it.group], n, lds);
+    mac_item<HT, G, NT>(T, it, n, lds);
     return;
   }
-  if (i >= A.phase_count[phase]) return;
+  // (the tail part of the grid is at most max_items long, and a phase's
+  // list is padded to max_items with K_NOP)
   const Item it = A.items[(int64_t)phase * A.max_items + i];
   if (it.kind == K_NOP) return;
   DevTier T = A.tier[it.tier];
@@ -1384,7 +1384,7 @@ __global__ __launch_bounds__(kThreads) void k_block(const KArgs A) {
     // later tier: the frame whose input completed in block n - lag
     frame = (n - it.lag + 1) / T.r - 1;
   }
-  mac_item<HT, G, NT>(A.Q, T, it, A.groups[it.group], frame, lds);
+  mac_item<HT, G, NT>(T, it, frame, lds);
 }
 
 // Graph replay's device block counter: set to v (add = 0), or advanced by v

@@ -100,6 +100,7 @@ struct TierHost {
   float2* tfwd = nullptr;    // tiers >= 1: transform scratch [Q][P] and [L][P]
   float2* tinv = nullptr;
   int nslots = 0;
+  int64_t h_rows = 0;        // spectrum rows allocated in H
   std::vector<int64_t> row;  // host copies
   std::vector<int32_t> kp;
 };
@@ -495,6 +496,22 @@ int build_plan(rta_ctx* c, Plan& plan) {
     for (int l = gr.l0; l < gr.l0 + gr.nl; ++l) kg = std::max(kg, T.kp[l * c->Q + q]);
     return kg;
   };
+  // a multiply-accumulate item's per-output spectrum rows (Item::row, pend)
+  auto mac_rows = [&](Item& it, const TierHost& T) {
+    const Group& gr = plan.groups[it.group];
+    it.nl = gr.nl;
+    for (int g = 0; g < 4; ++g) {
+      it.pend[g] = 0;
+      it.row[g] = 0;
+    }
+    for (int g = 0; g < gr.nl; ++g) {
+      const size_t pair = (size_t)(gr.l0 + g) * c->Q + it.q;
+      if (T.row[pair] >= 0) {
+        it.row[g] = T.row[pair];
+        it.pend[g] = std::min(it.p1, T.kp[pair]);
+      }
+    }
+  };
 
   // ---- first tier: partitions >= 2, every phase
   std::vector<Item> tier0;
@@ -605,6 +622,7 @@ int build_plan(rta_ctx* c, Plan& plan) {
             it.k0 = sl * W;
             it.w = W;
             it.slot = it_slot;
+            mac_rows(it, T);
             tier0.push_back(it);
           }
           if (!fixed) {
@@ -761,6 +779,7 @@ int build_plan(rta_ctx* c, Plan& plan) {
           it.slot = chunks[i].slot;
           it.acc = chunks[i].acc;
           it.lag = lag;
+          mac_rows(it, T);
           tier_mac[(ph0 + lag) % n_phase].push_back(it);
         }
       }
@@ -806,6 +825,11 @@ int build_plan(rta_ctx* c, Plan& plan) {
       if (it.p0 < (it.tier == 0 ? 2 : 0) || it.p1 < it.p0 || it.p1 > T.K) return RTA_E_STATE;
       if (W < C || W > kThreads * C || (W & (W - 1)) != 0 || T.P % W != 0) return RTA_E_STATE;
       if (it.k0 < 0 || it.k0 % W != 0 || it.k0 + W > T.P) return RTA_E_STATE;
+      if (it.nl != plan.groups[it.group].nl) return RTA_E_STATE;
+      for (int g = 0; g < it.nl; ++g)
+        if (it.pend[g] < 0 || it.pend[g] > it.p1 || it.row[g] < 0 ||
+            (it.pend[g] > 0 && it.row[g] + it.pend[g] > T.h_rows))
+          return RTA_E_STATE;
       if (it.tier == 0) {
         const Group& gr = plan.groups[it.group];
         if (it.slot < gr.slot0 || it.slot >= gr.slot0 + gr.nslot) return RTA_E_STATE;
@@ -1390,7 +1414,8 @@ int create_impl(rta_ctx* c, const std::vector<int>& size, const std::vector<int>
       for (int32_t kp : T.kp) tail_rows += std::max(0, kp - 2);
       c->tail_bytes = tail_rows * T.P * eb + (double)c->Q * std::max(0, kmax - 2) * T.P * 8.0;
     }
-    if ((st = dev_alloc(c, reinterpret_cast<char**>(&T.H), (size_t)std::max<int64_t>(1, rows) * T.P * eb)) != RTA_OK)
+    T.h_rows = std::max<int64_t>(1, rows);
+    if ((st = dev_alloc(c, reinterpret_cast<char**>(&T.H), (size_t)T.h_rows * T.P * eb)) != RTA_OK)
       return st;
     if ((st = dev_alloc(c, &T.pair_row, T.row.size())) != RTA_OK) return st;
     if ((st = dev_alloc(c, &T.pair_K, T.kp.size())) != RTA_OK) return st;
