@@ -1336,8 +1336,9 @@ __global__ __launch_bounds__(kThreads) void k_block(const KArgs A) {
     }
     return;
   }
-  // later tiers' transform passes of this phase, then the tails
-  const int phase = (int)(n % A.n_phase);
+  // later tiers' transform passes of this phase, then the tails (uniform
+  // partitions: one phase, no 64-bit division)
+  const int phase = A.n_phase == 1 ? 0 : (int)(n % A.n_phase);
   b -= A.head_slots;
   if (b < A.tier_slots) {
     if (b < A.tier_count[phase])
@@ -1372,10 +1373,12 @@ __global__ __launch_bounds__(kThreads) void k_block(const KArgs A) {
     return;
   }
   // (the tail part of the grid is at most max_items long, and a phase's
-  // list is padded to max_items with K_NOP)
+  // list is padded to max_items with K_NOP).  The first tier's fields are
+  // read before the item arrives: most items are first-tier ones.
+  DevTier T = A.tier[0];
   const Item it = A.items[(int64_t)phase * A.max_items + i];
   if (it.kind == K_NOP) return;
-  DevTier T = A.tier[it.tier];
+  if (it.tier != 0) T = A.tier[it.tier];
   int64_t frame;
   if (it.tier == 0) {
     frame = n + 1;  // first-tier tails prepare the next block
