@@ -662,6 +662,21 @@ __device__ __forceinline__ void head_work(const KArgs& A, int64_t n, const Group
   // twiddles for the FFTs: requested now, written to LDS after the partial-sum
   // reduction (its loads then share the round trip); published by the
   // barrier before the first FFT
+  {
+    // the prologue's kernel-argument fields in one batch (as in k_block)
+    const void* p0 = A.hist;
+    const void* p1 = A.in;
+    const void* p2 = A.sub;
+    const void* p3 = A.live;
+    const void* p4 = A.H01;
+    const void* p5 = A.tier[1].oring;
+    const void* p6 = A.tier[2].oring;
+    const int64_t m0 = A.hist_mask, m1 = A.ring_mask;
+    const int i0 = A.head_nq, i1 = A.Q, i2 = A.B, i3 = A.fc_on, i4 = A.n_tiers;
+    asm volatile("" ::"s"(T.tw), "s"(T.X), "s"(T.partial), "s"(T.K), "s"(T.P), "s"(T.logP), "s"(T.r3),
+                 "s"(T.nslots), "s"(p0), "s"(p1), "s"(p2), "s"(p3), "s"(p4), "s"(p5), "s"(p6), "s"(m0), "s"(m1),
+                 "s"(i0), "s"(i1), "s"(i2), "s"(i3), "s"(i4));
+  }
   const TwRegs twr = load_twiddles_regs(T);
   const float2* tw = twr.n > 0 ? lds + L.tw : stage_twiddles(T, lds + L.tw);
   const HT* H01 = reinterpret_cast<const HT*>(A.H01);
@@ -1317,6 +1332,19 @@ __global__ __launch_bounds__(kThreads) void k_block(const KArgs A) {
   extern __shared__ float2 lds[];
   // the block index: from the launch, or (graph replay) the device counter
   // plus this launch's place in the graph
+  // Kernel-argument fields are read where first used, after the branch
+  // before them, one scalar round trip after another; an empty asm that
+  // takes the dispatch's fields as operands makes them one batch up front.
+  {
+    const void* nb = A.n_base;
+    const int64_t n0 = A.n;
+    const int fc = A.fc_on, fs = A.fc.head_slots, fh = A.fc.n_heads, hs = A.head_slots, nh = A.n_head,
+              ts = A.tier_slots, np = A.n_phase, mi = A.max_items, tw = A.tails_wait;
+    const void* it = A.items;
+    const void* gr = A.groups;
+    asm volatile("" ::"s"(nb), "s"(n0), "s"(fc), "s"(fs), "s"(fh), "s"(hs), "s"(nh), "s"(ts), "s"(np), "s"(mi),
+                 "s"(tw), "s"(it), "s"(gr));
+  }
   const int64_t n = A.n_base != nullptr ? *A.n_base + A.n : A.n;
   int b = blockIdx.x;
   if (A.fc_on) {  // grid: feedback heads | heads | transforms | tails | feedback tails
@@ -1376,6 +1404,7 @@ __global__ __launch_bounds__(kThreads) void k_block(const KArgs A) {
   // list is padded to max_items with K_NOP).  The first tier's fields are
   // read before the item arrives: most items are first-tier ones.
   DevTier T = A.tier[0];
+  asm volatile("" ::"s"(T.H), "s"(T.X), "s"(T.partial), "s"(T.K), "s"(T.P), "s"(T.nslots));
   const Item it = A.items[(int64_t)phase * A.max_items + i];
   if (it.kind == K_NOP) return;
   if (it.tier != 0) T = A.tier[it.tier];
