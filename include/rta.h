@@ -181,13 +181,21 @@ int rta_create(rta_ctx** out, double fs, int32_t block,
  *                      tiers and at least 64 outputs, else 2 with at least
  *                      16 outputs, else 1).
  *   tail_items         target number of first-tier multiply-accumulate work
- *                      items per block (default 512).
+ *                      items per block (default 512).  With tail_rows unset,
+ *                      items get at least as many partitions as keep every
+ *                      output group's partial slots within what its output
+ *                      workgroup adds up from registers (16 per thread,
+ *                      256 / (bins per row) threads per bin), where the
+ *                      block size and inputs allow it.
  *   tail_rows          partitions per first-tier item; overrides tail_items.
  *   tier_rows          partitions per later-tier item (default 16).
  *   bin_slices         S in {1, 2, 4, 8}: first-tier items cover 1/S of a
  *                      partition row's bins over S times more rows, so each
  *                      output group owns S times fewer partial sums for the
- *                      output workgroups to reduce (default 1).
+ *                      output workgroups to reduce (default: 1, or, when the
+ *                      slot limit above has lengthened the items, a power
+ *                      of two that brings them back to about 32 KB of rows
+ *                      each; rta_info reports the choice).
  *   spectra_loads      how the multiply-accumulate streams the spectra:
  *                      1 = non-temporal loads, 2 = ordinary loads, 0 =
  *                      default (ordinary for uniform partitions, which
