@@ -1960,6 +1960,20 @@ int create_ctx(rta_ctx** out, double fs, int32_t block, const std::vector<int>& 
   // 128/1024/8192): about 512 first-tier items, two outputs per workgroup
   // from 16 outputs on, four with later tiers and 64 outputs or more
   c->G = (size.size() > 1 && n_out >= 64) ? 4 : n_out >= 16 ? 2 : 1;
+  // 16-bit spectra larger than half the 256 MB Infinity Cache stream mostly
+  // from HBM even in a context of their own; there the delay-line reads
+  // (FP32, through the vector caches) weigh more than the halved spectrum
+  // bytes, and four outputs per read with two bin slices pay (measured with
+  // the cache defeated, 1 -> 64 x 576,000 taps FP16: 33.1 -> 31.0 us per
+  // block; in one context unchanged)
+  if (size.size() == 1 && spectra != RTA_FP32 && cfg == nullptr && !(flags & RTA_FLAG_NF3) && n_out >= 32) {
+    double rows = 0;
+    for (int64_t i = 0; i < (int64_t)n_in * n_out; ++i) rows += (double)((lengths[i] + block - 1) / block);
+    if (rows * block * 4.0 > 128.0 * (1 << 20)) {
+      c->G = 4;
+      c->bin_slices = 2;
+    }
+  }
   if (tuning != nullptr) {
     if (tuning->outputs_per_group) c->G = tuning->outputs_per_group;
     if (tuning->tail_items) c->tail_items = tuning->tail_items;
