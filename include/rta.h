@@ -178,8 +178,9 @@ int rta_create(rta_ctx** out, double fs, int32_t block,
  * output up to FP32 rounding order).  Zero in any field selects the default.
  *   outputs_per_group  G in {1, 2, 4}: outputs sharing one input-spectrum
  *                      load in the multiply-accumulate (default 4 with later
- *                      tiers and at least 64 outputs, else 2 with at least
- *                      16 outputs, else 1).
+ *                      tiers and at least 64 outputs, and with uniform
+ *                      partitions, 16-bit spectra over 128 MB and at least
+ *                      32 outputs; else 2 with at least 16 outputs, else 1).
  *   tail_items         target number of first-tier multiply-accumulate work
  *                      items per block (default 512).  With tail_rows unset,
  *                      items get at least as many partitions as keep every
@@ -192,10 +193,11 @@ int rta_create(rta_ctx** out, double fs, int32_t block,
  *   bin_slices         S in {1, 2, 4, 8}: first-tier items cover 1/S of a
  *                      partition row's bins over S times more rows, so each
  *                      output group owns S times fewer partial sums for the
- *                      output workgroups to reduce (default: 1, or, when the
- *                      slot limit above has lengthened the items, a power
- *                      of two that brings them back to about 32 KB of rows
- *                      each; rta_info reports the choice).
+ *                      output workgroups to reduce (default: 2 where G = 4
+ *                      is chosen for 16-bit spectra as above; else 1, or,
+ *                      when the slot limit above has lengthened the items,
+ *                      a power of two that brings them back to about 32 KB
+ *                      of rows each; rta_info reports the choice).
  *   spectra_loads      how the multiply-accumulate streams the spectra:
  *                      1 = non-temporal loads, 2 = ordinary loads, 0 =
  *                      default (ordinary for uniform partitions, which
