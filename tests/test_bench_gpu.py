@@ -1,7 +1,8 @@
 """The benchmark run exactly as it is invoked for the record (one GPU, 20
 timed steps after 5 warm-up steps), in-process: it must print one JSON line
-with a positive roofline fraction and a CPU baseline whose comparison of the
-GPU output against the oracle meets the FP32 bound."""
+with a positive roofline fraction, the cache-defeating roofline leg, and a
+CPU baseline whose comparison of the GPU output against the oracle meets the
+FP32 bound."""
 import json
 
 import pytest
@@ -24,6 +25,11 @@ def test_bench_with_the_recording_arguments(capsys):
     assert res["value"] > 1.0
     assert res["roofline"]["frac"] > 0.0
     assert res["roofline"]["achieved"] > 0.0
+    # the cache-defeating leg: main's 123 MB of FP32 spectra need 4 contexts
+    # (1.5 x the 256 MB Infinity Cache), and can only be slower per block
+    honest = res["roofline_hbm_honest"]
+    assert honest["contexts"] >= 3 and honest["working_set_bytes"] >= 1.5 * (256 << 20)
+    assert 0.0 < honest["frac"] <= res["roofline"]["frac"] * 1.05
     cpu = res["cpu_baseline"]
     assert cpu["kind"] == "oracle" and cpu["cores"] >= 1 and cpu["value"] > 0
     assert cpu["gpu_error_db"]["max"] <= -100.0
