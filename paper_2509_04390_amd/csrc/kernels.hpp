@@ -533,7 +533,9 @@ __device__ __forceinline__ void red_issue(const KArgs& A, const DevTier& T, cons
   const int64_t stride = (int64_t)G * P;
   const float2* base = T.partial + (int64_t)grp.slot0 * stride;
   const int tid = threadIdx.x;
-  const int ng = kThreads / E, tg = tid / E, e = tid % E;
+  // (off the split path E may exceed kThreads; the loads then all read the
+  // dummy address and these only have to be defined)
+  const int ng = max(1, kThreads / E), tg = tid / E, e = tid % E;
   const int per = (grp.nslot + ng - 1) / ng;
   const int s0 = min(grp.nslot, tg * per);
   // Always kSlots loads, at clamped indices (a valid dummy address when the
