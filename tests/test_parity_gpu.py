@@ -207,9 +207,10 @@ def test_small_config_fp32_streamed_and_tail(rta):
     check_db(y[:, idx], refd, FP32_DB, "small/direct")
 
 
-@pytest.mark.parametrize("B,L,taps", [(128, 1, 200_000), (128, 4, 60_000), (256, 1, 65_536),
-                                         (64, 2, 40_000)])
-def test_few_outputs_long_filters_slot_capped_plan(rta, B, L, taps):
+@pytest.mark.parametrize("B,L,taps,spectra", [(128, 1, 200_000, "fp32"), (128, 4, 60_000, "fp32"),
+                                                 (256, 1, 65_536, "fp32"), (64, 2, 40_000, "fp32"),
+                                                 (128, 1, 200_000, "fp16"), (128, 2, 100_000, "bf16")])
+def test_few_outputs_long_filters_slot_capped_plan(rta, B, L, taps, spectra):
     """Few outputs and long filters: the default plan caps the partial slots of
     an output group at what a head adds up from registers (16 per thread,
     256 / P threads per bin) and slices the rows' bins to keep items small.
@@ -218,18 +219,19 @@ def test_few_outputs_long_filters_slot_capped_plan(rta, B, L, taps):
     filt = make_filters(B + L, lens)
     n = -(-(taps + 4 * B) // B) * B  # past the filter length: every partition live
     x = workloads.white_noise(B + L + 7, 1, n)
-    with rta.Convolver(filt, B) as cv:
+    with rta.Convolver(filt, B, spectra=spectra) as cv:
         info = cv.info()
         y = cv.run_device(x)
     P = B  # n_f = 2B: P bins per row
     cap = 16 * (256 // P)
-    say(f"B={B} L={L} taps={taps}: rows/item {info['rows_per_item']}, bin slices "
+    say(f"B={B} L={L} taps={taps} {spectra}: rows/item {info['rows_per_item']}, bin slices "
         f"{info['bin_slices']}, slots per group {info['max_group_slots']} (cap {cap}), grid {info['grid']}")
     assert 0 < info["max_group_slots"] <= cap
     rng = np.random.default_rng(B + L)
     idx = np.unique(np.r_[0, B - 1, B, 2 * B, taps - 1, taps, n - B, n - 1, rng.integers(0, n, 300)])
     ref = oracle.direct_at(x, filt, idx)
-    check_db(y[:, idx], ref, FP32_DB, f"B={B} L={L}")
+    limit = {"fp32": FP32_DB, "fp16": FP16_DB, "bf16": BF16_DB}[spectra]
+    check_db(y[:, idx], ref, limit, f"B={B} L={L} {spectra}")
 
 
 def test_main_config_full_size_sampled(rta):
