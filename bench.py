@@ -122,11 +122,22 @@ def cpu_baseline(wl, filt, x, max_channels: int, y_gpu=None, reps: int = 3):
     dt = float(np.median(times))
     audio_s = x.shape[1] / wl.fs
     full_s = dt * L / nch
+    # one thread: the oracle runs one output per thread, so one output alone
+    # is the one-thread time per output
+    one = [row[:1] for row in filt]
+    t0 = time.perf_counter()
+    oracle.fftols(x, one, x.shape[1])
+    one_s = (time.perf_counter() - t0) * L
+    taps_total = sum(len(f_) for row in filt for f_ in row if f_ is not None)
     cpu = host_cpu()
     res = {
         "value": audio_s / full_s,
         "unit": "x real-time (audio s / wall s)",
         "cores": min(threads, nch),
+        "wall_s": full_s,
+        "channel_filter_seconds_per_s": taps_total / wl.fs * audio_s / full_s,
+        "one_thread": {"value": audio_s / one_s, "wall_s": one_s,
+                       "speedup_on_cores": one_s / full_s},
         "kind": "oracle",
         "sample": (f"FP64 single-partition FFT overlap-save (the oracle as committed) over the "
                    f"workload's whole signal, {x.shape[1]} samples ({audio_s:.2f} s), for "
@@ -729,8 +740,9 @@ def main(argv=None) -> int:
         log(f"timing the oracle on the host cores over {nb_full} blocks ...")
         cpu = cpu_baseline(wl, filt, x_full[:, :nb_full * B], args.cpu_channels, y_gpu)
         log(f"cpu baseline: {cpu['value']:.2f} x real time on {cpu['cores']} threads "
-            f"({cpu['host']['model']}, nproc {cpu['host']['nproc']}); GPU error "
-            f"{cpu['gpu_error_db']['max']:.1f} dB max")
+            f"({cpu['host']['model']}, nproc {cpu['host']['nproc']}; one thread "
+            f"{cpu['one_thread']['value']:.2f} x, {cpu['one_thread']['speedup_on_cores']:.1f}x "
+            f"speedup); GPU error {cpu['gpu_error_db']['max']:.1f} dB max")
 
     n_h = wl.max_len()
     lens = [int(np.asarray(f).size) for row in filt for f in row]

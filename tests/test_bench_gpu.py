@@ -32,5 +32,7 @@ def test_bench_with_the_recording_arguments(capsys):
     assert 0.0 < honest["frac"] <= res["roofline"]["frac"] * 1.05
     cpu = res["cpu_baseline"]
     assert cpu["kind"] == "oracle" and cpu["cores"] >= 1 and cpu["value"] > 0
+    assert cpu["wall_s"] > 0 and cpu["channel_filter_seconds_per_s"] > 0
+    assert 0 < cpu["one_thread"]["value"] <= cpu["value"] * 1.5
     assert cpu["gpu_error_db"]["max"] <= -100.0
     assert cpu["gpu_error_db"]["samples"] == 2000 * 128
