@@ -718,6 +718,21 @@ def main(argv=None) -> int:
                         + info["io_bytes_per_block"])
     achieved = bytes_per_launch / (kern_us * 1e-6) / 1e9
     traffic = measured_traffic(wl.name, args.spectra)
+    # arithmetic per block: 8 real flops per complex multiply-accumulate, and
+    # (reported apart) about 2.5 N log2 N per real N-point FFT for the Q
+    # forward and L inverse transforms of each tier (2 P_t points; later tiers
+    # once per P_t / B blocks)
+    fft_flops = 0.0
+    for t, P_t in enumerate(info["tier_size"]):
+        N_t = 2 * P_t  # (3B points with n_f = 3B, where P = 3B/2)
+        per_block = 1.0 if t == 0 else B / P_t  # the first tier's frame is every block
+        fft_flops += (Q + L) * per_block * 2.5 * N_t * np.log2(N_t)
+    cmac_flops = 8.0 * info["cmacs_per_block"]
+    flops = {"cmac_per_block": cmac_flops, "fft_per_block": fft_flops,
+             "cmac_gflops": cmac_flops / (kern_us * 1e3),
+             "flops_per_byte": cmac_flops / bytes_per_launch,
+             "note": "8 flops per complex multiply-accumulate; FFTs at 2.5 N log2 N per real "
+                     "N-point transform (Q forward, L inverse per tier and frame)"}
     honest = hbm_honest_leg(args, torch, rta, cv, info,
                             lambda: rta.Convolver(filt, B, fs=fs, spectra=args.spectra, scheme=scheme,
                                                   tuning=tuning),
@@ -775,6 +790,7 @@ def main(argv=None) -> int:
         },
         "rtf": (ms_per_step / 1e3) / audio_per_step,
         "channel_filter_seconds_per_s": taps_total / fs * value,
+        "flops": flops,
         "deadline_us": deadline,
         "latency": paced,
         "latency_back_to_back": None if not len(lat_us) else {
