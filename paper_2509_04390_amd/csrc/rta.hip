@@ -1966,13 +1966,12 @@ int create_ctx(rta_ctx** out, double fs, int32_t block, const std::vector<int>& 
   // bytes, and four outputs per read with two bin slices pay (measured with
   // the cache defeated, 1 -> 64 x 576,000 taps FP16: 33.1 -> 31.0 us per
   // block; in one context unchanged)
+  bool big16 = false;
   if (size.size() == 1 && spectra != RTA_FP32 && cfg == nullptr && !(flags & RTA_FLAG_NF3) && n_out >= 32) {
     double rows = 0;
     for (int64_t i = 0; i < (int64_t)n_in * n_out; ++i) rows += (double)((lengths[i] + block - 1) / block);
-    if (rows * block * 4.0 > 128.0 * (1 << 20)) {
-      c->G = 4;
-      c->bin_slices = 2;
-    }
+    big16 = rows * block * 4.0 > 128.0 * (1 << 20);
+    if (big16) c->G = 4;
   }
   if (tuning != nullptr) {
     if (tuning->outputs_per_group) c->G = tuning->outputs_per_group;
@@ -1982,6 +1981,8 @@ int create_ctx(rta_ctx** out, double fs, int32_t block, const std::vector<int>& 
     if (tuning->bin_slices) c->bin_slices = tuning->bin_slices;
     c->spectra_loads = tuning->spectra_loads;
   }
+  // (the two slices go with the four outputs per read, unless the caller chose)
+  if (big16 && c->G == 4 && c->bin_slices == 0) c->bin_slices = 2;
   if (cfg != nullptr) {
     c->serve = new (std::nothrow) Serve();
     if (c->serve == nullptr) {
