@@ -193,8 +193,9 @@ int rta_create(rta_ctx** out, double fs, int32_t block,
  *   bin_slices         S in {1, 2, 4, 8}: first-tier items cover 1/S of a
  *                      partition row's bins over S times more rows, so each
  *                      output group owns S times fewer partial sums for the
- *                      output workgroups to reduce (default: 2 where G = 4
- *                      is chosen for 16-bit spectra as above; else 1, or,
+ *                      output workgroups to reduce (default: 2 for 16-bit
+ *                      spectra with uniform partitions and at least 32
+ *                      outputs, outside serving and n_f = 3B; else 1, or,
  *                      when the slot limit above has lengthened the items,
  *                      a power of two that brings them back to about 32 KB
  *                      of rows each; rta_info reports the choice).
