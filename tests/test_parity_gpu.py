@@ -234,6 +234,31 @@ def test_few_outputs_long_filters_slot_capped_plan(rta, B, L, taps, spectra):
     check_db(y[:, idx], ref, limit, f"B={B} L={L} {spectra}")
 
 
+@pytest.mark.parametrize("L,spectra,tuning_slices,want", [(32, "fp16", 0, 2), (40, "bf16", 0, 2),
+                                                        (32, "fp32", 0, 1), (16, "fp16", 0, 1),
+                                                        (32, "fp16", 1, 1), (32, "fp16", 4, 4)])
+def test_tiling_default_slices_for_16bit(rta, L, spectra, tuning_slices, want):
+    """Uniform partitions with 16-bit spectra and at least 32 outputs take two
+    bin slices unless the caller sets them; FP32 spectra and fewer outputs keep
+    one.  rta_info reports the layout, and the output matches the oracle."""
+    B, taps = 128, 20_000
+    filt = make_filters(L + 3, [[taps] * L])
+    n = -(-(taps + 4 * B) // B) * B
+    x = workloads.white_noise(L + 11, 1, n)
+    tun = rta.make_tuning(bin_slices=tuning_slices) if tuning_slices else None
+    with rta.Convolver(filt, B, spectra=spectra, tuning=tun) as cv:
+        info = cv.info()
+        y = cv.run_device(x)
+    say(f"L={L} {spectra} slices asked {tuning_slices}: bin slices {info['bin_slices']}, "
+        f"outputs per group {info['outputs_per_group']}, grid {info['grid']}")
+    assert info["bin_slices"] == want
+    rng = np.random.default_rng(L)
+    idx = np.unique(np.r_[0, B - 1, B, taps - 1, taps, n - 1, rng.integers(0, n, 200)])
+    ref = oracle.direct_at(x, filt, idx)
+    limit = {"fp32": FP32_DB, "fp16": FP16_DB, "bf16": BF16_DB}[spectra]
+    check_db(y[:, idx], ref, limit, f"L={L} {spectra} slices {info['bin_slices']}")
+
+
 def test_main_config_full_size_sampled(rta):
     """1 input -> 32 outputs, 480,000-tap filters, block 128, 2,000 blocks."""
     wl = workloads.config("main")
