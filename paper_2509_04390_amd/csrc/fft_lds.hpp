@@ -176,6 +176,37 @@ __device__ __forceinline__ constexpr int brev_small(int s) {
                                         : ((s & 1) << 2) | (s & 2) | (s >> 2);
 }
 
+// v of lane (lane ^ H) for a butterfly partner at distance H: quad
+// permutations (DPP, a VALU operand modifier) for 1 and 2, the LDS
+// crossbar's swizzle (bit mode, xor mask; no address operand) for 4 to 16,
+// a backward permute for 32.
+template <int H>
+__device__ __forceinline__ float lane_xor(float v, int lane) {
+  const int i = __float_as_int(v);
+  int o;
+  if constexpr (H == 1)
+    o = __builtin_amdgcn_mov_dpp(i, 0xB1, 0xF, 0xF, false);  // quad_perm [1, 0, 3, 2]
+  else if constexpr (H == 2)
+    o = __builtin_amdgcn_mov_dpp(i, 0x4E, 0xF, 0xF, false);  // quad_perm [2, 3, 0, 1]
+  else if constexpr (H < 32)
+    o = __builtin_amdgcn_ds_swizzle(i, 0x1F | (H << 10));  // and 0x1f, or 0, xor H
+  else
+    o = __builtin_amdgcn_ds_bpermute((lane ^ H) << 2, i);
+  return __int_as_float(o);
+}
+// One radix-2 DIF stage across lanes at distance H for V registers per lane.
+template <bool INV, int V, int H>
+__device__ __forceinline__ void wave_stage(float2 (&r)[V], int N, const float2* __restrict__ tw, int lane) {
+  const bool hi = (lane & H) != 0;
+  float2 w = tw[(lane & (H - 1)) * (N / (2 * H))];
+  if (INV) w.y = -w.y;
+#pragma unroll
+  for (int s = 0; s < V; ++s) {
+    const float2 p = make_float2(lane_xor<H>(r[s].x, lane), lane_xor<H>(r[s].y, lane));
+    r[s] = hi ? cmul(csub(p, r[s]), w) : cadd(r[s], p);
+  }
+}
+
 // One N = 64 V-point transform (V in {1, 2}; brev_small and the in-lane
 // stage also cover 4 and 8) by one wavefront, without barriers: lane i
 // holds x[64 v + i] (v < V) in registers, with n = 64 v + i and
@@ -183,8 +214,8 @@ __device__ __forceinline__ constexpr int brev_small(int s) {
 //   X[k1 + V k2] = sum_i W_64^{i k2} W_N^{i k1} sum_v x[64 v + i] W_V^{v k1}:
 // a V-point DIF in each lane's registers, the twiddles W_N^{i k1}, then a
 // 64-point radix-2 DIF across the lanes whose butterfly partners are
-// exchanged with lane shuffles (distance 32, 16, ..., 1).  Lane i then holds
-// k2 = bitrev6(i) and register s holds k1 = bitrev(s); each value is written
+// exchanged across lanes (distance 32, 16, ..., 1; lane_xor).  Lane i then
+// holds k2 = bitrev6(i) and register s holds k1 = bitrev(s); each value is written
 // to its natural place in `dst`.  `tw` = W_N^j (j < N); INV conjugates.
 template <bool INV, int V>
 __device__ __forceinline__ void fft_wave_one(const float2* __restrict__ src, float2* __restrict__ dst,
@@ -211,16 +242,12 @@ __device__ __forceinline__ void fft_wave_one(const float2* __restrict__ src, flo
   }
 #pragma unroll
   for (int s = 1; s < V; ++s) r[s] = cmul(r[s], twid(lane * brev_small<V>(s)));
-#pragma unroll
-  for (int h = 32; h >= 1; h >>= 1) {
-    const bool hi = (lane & h) != 0;
-    const float2 w = twid((lane & (h - 1)) * (N / (2 * h)));
-#pragma unroll
-    for (int s = 0; s < V; ++s) {
-      const float2 p = make_float2(__shfl_xor(r[s].x, h), __shfl_xor(r[s].y, h));
-      r[s] = hi ? cmul(csub(p, r[s]), w) : cadd(r[s], p);
-    }
-  }
+  wave_stage<INV, V, 32>(r, N, tw, lane);
+  wave_stage<INV, V, 16>(r, N, tw, lane);
+  wave_stage<INV, V, 8>(r, N, tw, lane);
+  wave_stage<INV, V, 4>(r, N, tw, lane);
+  wave_stage<INV, V, 2>(r, N, tw, lane);
+  wave_stage<INV, V, 1>(r, N, tw, lane);
   const int k2 = (int)(__brev((unsigned int)lane) >> 26);
 #pragma unroll
   for (int s = 0; s < V; ++s) dst[brev_small<V>(s) + V * k2] = r[s];
