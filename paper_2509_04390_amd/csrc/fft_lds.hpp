@@ -179,7 +179,7 @@ __device__ __forceinline__ constexpr int brev_small(int s) {
 // v of lane (lane ^ H) for a butterfly partner at distance H: quad
 // permutations (DPP, a VALU operand modifier) for 1 and 2, the LDS
 // crossbar's swizzle (bit mode, xor mask; no address operand) for 4 to 16,
-// a backward permute for 32.
+// the gfx950 half-wave swap (VALU) for 32.
 template <int H>
 __device__ __forceinline__ float lane_xor(float v, int lane) {
   const int i = __float_as_int(v);
@@ -190,8 +190,12 @@ __device__ __forceinline__ float lane_xor(float v, int lane) {
     o = __builtin_amdgcn_mov_dpp(i, 0x4E, 0xF, 0xF, false);  // quad_perm [2, 3, 0, 1]
   else if constexpr (H < 32)
     o = __builtin_amdgcn_ds_swizzle(i, 0x1F | (H << 10));  // and 0x1f, or 0, xor H
-  else
-    o = __builtin_amdgcn_ds_bpermute((lane ^ H) << 2, i);
+  else {
+    // half-wave swap of v with itself: the partner values are in the second
+    // result for lanes below 32, in the first for the others
+    const auto r = __builtin_amdgcn_permlane32_swap((unsigned)i, (unsigned)i, false, false);
+    o = (int)((lane & 32) ? r[0] : r[1]);
+  }
   return __int_as_float(o);
 }
 // One radix-2 DIF stage across lanes at distance H for V registers per lane.
